@@ -1,0 +1,14 @@
+"""MI355X-native critical-point classification of PL scalar fields on grids.
+
+The classification (Section 3.1 of Lukasczyk et al., "Localized Topological
+Simplification of Scalar Data", with the index tie-break of Section 4.1) runs
+in the HIP kernels of ``libpcrit.so``; this package only marshals arguments
+to its C ABI (``include/pcrit.h``).  PyTorch supplies device memory and
+streams.  There is no CPU fallback: if the library is missing, every call
+raises.
+"""
+from .binding import (  # noqa: F401
+    PcritError, Context, classify, progressive, max_level, level_dims,
+    link_table, preview_f1, library_path, decode, is_critical, point_type,
+    E_ARG, E_DIMS, E_LEVEL, E_CAPACITY, E_NAN, E_HIP, E_OOM,
+)

@@ -1,0 +1,336 @@
+"""ctypes binding of libpcrit.so (argument marshalling only).
+
+Every function forwards to the C ABI declared in ``include/pcrit.h``; the
+classification itself runs in the library's HIP kernels.  Device buffers are
+torch tensors on a ROCm device; the stream is torch's current stream unless
+one is given.  A missing library raises ``PcritError`` -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+E_ARG, E_DIMS, E_LEVEL, E_CAPACITY, E_NAN, E_HIP, E_OOM = -1, -2, -3, -4, -5, -6, -7
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpcrit.so")
+_lib = None
+
+EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
+            "pcrit_max_level", "pcrit_level_dims", "pcrit_link_table",
+            "pcrit_classify", "pcrit_progressive", "pcrit_set_kernel_timing",
+            "pcrit_kernel_ms", "pcrit_preview_f1")
+
+
+class PcritError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _strerror(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise PcritError(E_HIP, f"{_LIB_PATH} is not built "
+                                "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+    p64 = ctypes.POINTER(i64)
+    lib.pcrit_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.pcrit_create.restype = i32
+    lib.pcrit_destroy.argtypes = [vp]
+    lib.pcrit_destroy.restype = None
+    lib.pcrit_strerror.argtypes = [i32]
+    lib.pcrit_strerror.restype = ctypes.c_char_p
+    lib.pcrit_max_level.argtypes = [i64, i64, i64, ctypes.POINTER(i32)]
+    lib.pcrit_max_level.restype = i32
+    lib.pcrit_level_dims.argtypes = [i64, i64, i64, i32, vp]
+    lib.pcrit_level_dims.restype = i32
+    lib.pcrit_link_table.argtypes = [i32, vp, i64]
+    lib.pcrit_link_table.restype = i32
+    lib.pcrit_classify.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp, vp, vp,
+                                   i64, p64, vp]
+    lib.pcrit_classify.restype = i32
+    lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
+    lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
+                                      i64, vp, vp, vp, lib.LEVEL_CB, vp]
+    lib.pcrit_progressive.restype = i32
+    lib.pcrit_set_kernel_timing.argtypes = [vp, i32]
+    lib.pcrit_set_kernel_timing.restype = i32
+    lib.pcrit_kernel_ms.argtypes = [vp, vp, vp, i32]
+    lib.pcrit_kernel_ms.restype = i32
+    lib.pcrit_preview_f1.argtypes = [i64, i64, i64, i32, vp, vp, i64, vp, vp,
+                                     i64, ctypes.POINTER(ctypes.c_double), p64]
+    lib.pcrit_preview_f1.restype = i32
+    _lib = lib
+    return lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return _load().pcrit_strerror(status).decode()
+    except PcritError:
+        return f"status {status}"
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise PcritError(status, what)
+
+
+def _shape3(shape):
+    shape = tuple(int(s) for s in shape)
+    if len(shape) == 3:
+        nz, ny, nx = shape
+    elif len(shape) == 2:
+        (ny, nx), nz = shape, 1
+    else:
+        raise PcritError(E_DIMS, "field must be (nz, ny, nx) or (ny, nx)")
+    return nx, ny, nz
+
+
+def max_level(shape) -> int:
+    k = ctypes.c_int(0)
+    nx, ny, nz = _shape3(shape)
+    _check(_load().pcrit_max_level(nx, ny, nz, ctypes.byref(k)), "max_level")
+    return k.value
+
+
+def level_dims(shape, level: int):
+    """(n_x, n_y, n_z) samples of level `level`."""
+    m = np.zeros(3, np.int64)
+    nx, ny, nz = _shape3(shape)
+    _check(_load().pcrit_level_dims(nx, ny, nz, level, m.ctypes.data),
+           "level_dims")
+    return tuple(int(v) for v in m)
+
+
+def link_table(dim: int) -> np.ndarray:
+    """The host-built link-pattern table the kernels use (16384 or 64 B)."""
+    n = 1 << 14 if dim == 3 else 1 << 6
+    t = np.zeros(n, np.uint8)
+    _check(_load().pcrit_link_table(dim, t.ctypes.data, n), "link_table")
+    return t
+
+
+class Context:
+    """Owns the device lookup tables, scratch and events of one device."""
+
+    def __init__(self, device: int = 0):
+        lib = _load()
+        self._ptr = ctypes.c_void_p()
+        _check(lib.pcrit_create(ctypes.byref(self._ptr), int(device)),
+               "pcrit_create")
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            _load().pcrit_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_kernel_timing(self, enable: bool):
+        _check(_load().pcrit_set_kernel_timing(self._ptr, int(bool(enable))),
+               "set_kernel_timing")
+
+    def kernel_ms(self, max_levels: int = 40):
+        a = np.full(max_levels, -1, np.float32)
+        b = np.full(max_levels, -1, np.float32)
+        _check(_load().pcrit_kernel_ms(self._ptr, a.ctypes.data, b.ctypes.data,
+                                       max_levels), "kernel_ms")
+        return a, b
+
+
+_default_ctx = {}
+
+
+def _ctx_for(tensor, ctx):
+    if ctx is not None:
+        return ctx
+    dev = tensor.device.index or 0
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+def _stream_handle(tensor, stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(tensor.device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _check_field(field):
+    import torch
+    if not isinstance(field, torch.Tensor) or field.device.type != "cuda":
+        raise PcritError(E_ARG, "field must be a torch tensor on a ROCm device")
+    if field.dtype != torch.float32 or not field.is_contiguous():
+        raise PcritError(E_ARG, "field must be contiguous float32")
+    return _shape3(field.shape)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class ClassifyResult:
+    codes: "object"           # uint8 tensor, full resolution
+    crit: "object"            # int32 tensor (uint32 values), ascending
+    crit_codes: "object"      # uint8 tensor or None
+    count: int                # number of critical vertices
+    status: int
+
+
+def classify(field, level: int = 0, *, ctx: Optional[Context] = None,
+             capacity: Optional[int] = None, with_crit_codes: bool = False,
+             codes=None, crit=None, stream=None, count_dev=None,
+             check: bool = True) -> ClassifyResult:
+    """Classify every vertex of level `level` of `field` (direct pass).
+
+    With ``count_dev`` (an int64 device tensor of one element) the call is
+    asynchronous and the count is written there; otherwise it synchronises
+    and returns the count."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    lib = _load()
+    c = _ctx_for(field, ctx)
+    if codes is None:
+        codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
+    if capacity is None:
+        m = level_dims(field.shape, level)
+        capacity = m[0] * m[1] * m[2]
+    if crit is None:
+        crit = torch.empty(max(capacity, 1), dtype=torch.int32,
+                           device=field.device)
+    cc = (torch.empty(max(capacity, 1), dtype=torch.uint8, device=field.device)
+          if with_crit_codes else None)
+    cnt = ctypes.c_int64(-1)
+    st = lib.pcrit_classify(
+        c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
+        int(level), _ptr(codes), _ptr(crit), _ptr(cc), int(capacity),
+        None if count_dev is not None else ctypes.byref(cnt), _ptr(count_dev))
+    if check and st not in (0, E_CAPACITY):
+        raise PcritError(st, "pcrit_classify")
+    n = cnt.value
+    if count_dev is not None:
+        return ClassifyResult(codes, crit, cc, -1, st)
+    k = max(0, min(n, capacity))
+    return ClassifyResult(codes, crit[:k], None if cc is None else cc[:k], n,
+                          st)
+
+
+@dataclass
+class ProgressiveResult:
+    codes: "object"
+    crit: "object"              # concatenated lists, coarse to fine
+    crit_codes: "object"
+    levels: List[int]           # k_max .. 0
+    offsets: np.ndarray         # k_max + 2 entries
+    level_ms: np.ndarray        # cumulative ms at each level's completion
+    reclassified: np.ndarray    # old vertices re-classified per level
+    status: int
+
+    def level_list(self, level: int):
+        i = self.levels.index(level)
+        return self.crit[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+    def level_codes(self, level: int):
+        i = self.levels.index(level)
+        return self.crit_codes[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+
+def progressive(field, *, ctx: Optional[Context] = None,
+                capacity: Optional[int] = None, with_crit_codes: bool = False,
+                codes=None, crit=None, crit_codes=None, stream=None,
+                callback=None, check: bool = True) -> ProgressiveResult:
+    """Coarse-to-fine classification over every level of the hierarchy."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    lib = _load()
+    c = _ctx_for(field, ctx)
+    kmax = max_level(field.shape)
+    if capacity is None:
+        capacity = 0
+        for k in range(kmax + 1):
+            m = level_dims(field.shape, k)
+            capacity += m[0] * m[1] * m[2]
+    if codes is None:
+        codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
+    if crit is None:
+        crit = torch.empty(max(capacity, 1), dtype=torch.int32,
+                           device=field.device)
+    if with_crit_codes and crit_codes is None:
+        crit_codes = torch.empty(max(capacity, 1), dtype=torch.uint8,
+                                 device=field.device)
+    offs = np.zeros(kmax + 2, np.int64)
+    ms = np.zeros(kmax + 1, np.float32)
+    rec = np.zeros(kmax + 1, np.int64)
+    cb = lib.LEVEL_CB(callback) if callback else ctypes.cast(None, lib.LEVEL_CB)
+    st = lib.pcrit_progressive(
+        c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
+        _ptr(codes), _ptr(crit), _ptr(crit_codes), int(capacity),
+        offs.ctypes.data, ms.ctypes.data, rec.ctypes.data, cb, None)
+    if check and st not in (0, E_CAPACITY):
+        raise PcritError(st, "pcrit_progressive")
+    return ProgressiveResult(codes, crit, crit_codes,
+                             list(range(kmax, -1, -1)), offs, ms, rec, st)
+
+
+def preview_f1(shape, level: int, preview, preview_codes, exact, exact_codes):
+    """Host metric: (F1, matches) of a level-`level` preview list against the
+    exact list (numpy uint32 indices, uint8 codes)."""
+    nx, ny, nz = _shape3(shape)
+    p = np.ascontiguousarray(preview, dtype=np.uint32)
+    pc = np.ascontiguousarray(preview_codes, dtype=np.uint8)
+    e = np.ascontiguousarray(exact, dtype=np.uint32)
+    ec = np.ascontiguousarray(exact_codes, dtype=np.uint8)
+    f1 = ctypes.c_double(0)
+    mt = ctypes.c_int64(0)
+    _check(_load().pcrit_preview_f1(nx, ny, nz, int(level), p.ctypes.data,
+                                    pc.ctypes.data, len(p), e.ctypes.data,
+                                    ec.ctypes.data, len(e), ctypes.byref(f1),
+                                    ctypes.byref(mt)), "preview_f1")
+    return f1.value, mt.value
+
+
+def decode(codes):
+    """(n_lower, n_upper, boundary, hole) arrays from code bytes."""
+    c = np.asarray(codes).astype(np.int32)
+    return c & 7, (c >> 3) & 7, (c >> 6) & 1, (c >> 7) & 1
+
+
+def is_critical(codes):
+    c = np.asarray(codes).astype(np.int32)
+    return (c & 0xBF) != 0x09
+
+
+def point_type(codes):
+    """0 regular, 1 minimum, 2 maximum, 3 saddle."""
+    nl, nu, _, hole = decode(codes)
+    t = np.full(nl.shape, 3, np.int8)
+    t[(nl == 1) & (nu == 1) & (hole == 0)] = 0
+    t[nu == 0] = 2
+    t[nl == 0] = 1
+    return t

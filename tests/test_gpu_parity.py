@@ -1,0 +1,391 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results, so the bar is byte equality of the code array (at level
+positions) and of the ascending critical list.  Cases: every interior
+polarity pattern, every boundary class with every pattern of its present
+neighbours, the 64^3 Gaussian workload, ragged and tie-heavy grids at every
+level, the progressive driver per level, error paths, and the full-size
+workloads on every vertex, plus the padded Morse count.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle
+import paper_2009_00083_amd as pc
+
+pytestmark = pytest.mark.gpu
+
+OFF3 = [(0, 0, -1), (-1, 0, -1), (0, -1, -1), (-1, -1, -1),
+        (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (-1, -1, 0), (1, 1, 0),
+        (0, 0, 1), (1, 0, 1), (0, 1, 1), (1, 1, 1)]
+OFF2 = [(-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, 1)]
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    return pc.Context(0)
+
+
+def gpu_classify(ctx, dev, f, level=0, **kw):
+    ft = torch.from_numpy(np.ascontiguousarray(f)).to(dev)
+    r = pc.classify(ft, level, ctx=ctx, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+def level_mask(shape, level):
+    s = 1 << level
+    m = np.zeros(shape, bool)
+    m[tuple(slice(0, None, s) for _ in shape)] = True
+    return m
+
+
+def assert_same(f, level, r, ref, what=""):
+    codes = r.codes.cpu().numpy()
+    lm = level_mask(f.shape, level)
+    assert np.array_equal(codes[lm], ref.codes[lm]), f"codes differ {what}"
+    crit = r.crit.cpu().numpy().view(np.uint32)
+    assert np.array_equal(crit, ref.crit), f"list differs {what}"
+    assert r.count == ref.count
+
+
+# ---------------------------------------------------------------------------
+# Exhaustive patterns
+# ---------------------------------------------------------------------------
+def test_all_interior_patterns(ctx, dev):
+    bx, by, bz = 32, 32, 16
+    f = np.full((3 * bz, 3 * by, 3 * bx), 0.25, np.float32)
+    for b in range(1 << 14):
+        cx, cy, cz = 3 * (b % bx) + 1, 3 * ((b // bx) % by) + 1, 3 * (b // (bx * by)) + 1
+        f[cz, cy, cx] = 0.0
+        for j, (dx, dy, dz) in enumerate(OFF3):
+            f[cz + dz, cy + dy, cx + dx] = 1.0 if (b >> j) & 1 else -1.0
+    log("interior patterns", f.shape)
+    r = gpu_classify(ctx, dev, f)
+    assert_same(f, 0, r, oracle.classify(f), "interior patterns")
+
+
+def _boundary_classes(dim):
+    """(side per axis) with at least one cut side: -1 low, +1 high, 0 free."""
+    for sides in itertools.product((-1, 0, 1), repeat=dim):
+        if any(sides):
+            yield sides
+
+
+def _boundary_grids(sides, offsets):
+    """Grids placing every polarity pattern of the present neighbours at a
+    vertex of boundary class `sides`.  Cut axes have 2 samples (the centre on
+    the cut side), free axes pack patterns every 3 samples."""
+    dim = len(sides)
+    present = [j for j, o in enumerate(offsets)
+               if all(not (s == -1 and d == -1) and not (s == 1 and d == 1)
+                      for s, d in zip(sides, o))]
+    npat = 1 << len(present)
+    free = [a for a in range(dim) if sides[a] == 0]
+    per_grid = npat if free else 1
+    if len(free) == 2:
+        side_len = [int(np.ceil(np.sqrt(npat)))] * 2
+    elif len(free) == 1:
+        side_len = [npat]
+    else:
+        side_len = []
+    grids = []
+    for g0 in range(0, npat, per_grid):
+        ext = []
+        fi = 0
+        for a in range(dim):
+            if sides[a] == 0:
+                ext.append(3 * side_len[fi])
+                fi += 1
+            else:
+                ext.append(2)
+        f = np.full(tuple(reversed(ext)), 0.25, np.float32)  # C order
+        for p in range(g0, min(npat, g0 + per_grid)):
+            q = p - g0
+            centre = []
+            fi = 0
+            for a in range(dim):
+                if sides[a] == -1:
+                    centre.append(0)
+                elif sides[a] == 1:
+                    centre.append(1)
+                else:
+                    if fi == 0:
+                        centre.append(3 * (q % side_len[0]) + 1)
+                    else:
+                        centre.append(3 * (q // side_len[0]) + 1)
+                    fi += 1
+            f[tuple(reversed(centre))] = 0.0
+            for bit, j in enumerate(present):
+                nb = tuple(c + d for c, d in zip(centre, offsets[j]))
+                f[tuple(reversed(nb))] = 1.0 if (p >> bit) & 1 else -1.0
+        grids.append(f)
+    return grids
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_all_boundary_patterns(ctx, dev, dim):
+    offsets = OFF3 if dim == 3 else OFF2
+    ncalls = 0
+    for sides in _boundary_classes(dim):
+        for f in _boundary_grids(sides, offsets):
+            r = gpu_classify(ctx, dev, f)
+            assert_same(f, 0, r, oracle.classify(f, threads=1), f"class {sides}")
+            ncalls += 1
+    log("boundary classes checked with", ncalls, "grids")
+
+
+# ---------------------------------------------------------------------------
+# Workloads and ragged grids, direct
+# ---------------------------------------------------------------------------
+def test_gauss64_direct(ctx, dev):
+    f = fieldgen.config_field("gauss64")
+    r = gpu_classify(ctx, dev, f, with_crit_codes=True)
+    ref = oracle.classify(f)
+    assert_same(f, 0, r, ref, "gauss64")
+    cc = r.crit_codes.cpu().numpy()
+    assert np.array_equal(cc, ref.codes.ravel()[ref.crit])
+
+
+RAGGED = [(37, 23, 19), (3, 64, 65), (66, 5, 130), (2, 2, 2), (9, 2, 70),
+          (19, 33, 129), (301, 77), (2, 1000), (1000, 2), (65, 257), (5, 5)]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+@pytest.mark.parametrize("gen", ["tie", "gauss"])
+def test_ragged_all_levels_direct(ctx, dev, shape, gen):
+    f = (fieldgen.tie_field(shape, 3, 3) if gen == "tie" else
+         fieldgen.gaussian_field(shape, 4, 5, noise=("uniform", 1e-3)))
+    for level in range(pc.max_level(shape) + 1):
+        r = gpu_classify(ctx, dev, f, level)
+        assert_same(f, level, r, oracle.classify(f, level=level),
+                    f"{shape} level {level}")
+
+
+def test_special_values(ctx, dev):
+    """+-inf are ordinary values; -0 equals +0 (ties go to the index)."""
+    f = fieldgen.tie_field((11, 12, 13), 9, 4)
+    vals = np.array([-np.inf, -0.0, 0.0, np.inf, 1.0], np.float32)
+    f = vals[f.astype(np.int64) % 5].astype(np.float32)
+    f.ravel()[::7] = -0.0
+    r = gpu_classify(ctx, dev, f)
+    assert_same(f, 0, r, oracle.classify(f), "special values")
+
+
+# ---------------------------------------------------------------------------
+# Progressive
+# ---------------------------------------------------------------------------
+def check_progressive(ctx, dev, f, per_level_oracle=True):
+    ft = torch.from_numpy(np.ascontiguousarray(f)).to(dev)
+    p = pc.progressive(ft, ctx=ctx, with_crit_codes=True)
+    torch.cuda.synchronize()
+    assert p.status == 0
+    crit_all = p.crit.cpu().numpy().view(np.uint32)
+    cc_all = p.crit_codes.cpu().numpy()
+    for i, k in enumerate(p.levels):
+        lst = crit_all[p.offsets[i]:p.offsets[i + 1]]
+        if per_level_oracle:
+            ref = oracle.classify(f, level=k)
+            assert np.array_equal(lst, ref.crit), f"level {k} list"
+            assert np.array_equal(cc_all[p.offsets[i]:p.offsets[i + 1]],
+                                  ref.codes.ravel()[ref.crit]), f"level {k} codes"
+    d = pc.classify(ft, 0, ctx=ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(p.codes.cpu().numpy(), d.codes.cpu().numpy())
+    assert np.array_equal(crit_all[p.offsets[-2]:p.offsets[-1]],
+                          d.crit.cpu().numpy().view(np.uint32))
+    return p
+
+
+@pytest.mark.parametrize("shape", [(37, 23, 19), (33, 33, 33), (66, 5, 130),
+                                   (2, 2, 2), (17, 9, 40), (301, 77), (2, 1000),
+                                   (129, 130)])
+@pytest.mark.parametrize("gen", ["tie", "gauss"])
+def test_progressive_small(ctx, dev, shape, gen):
+    f = (fieldgen.tie_field(shape, 5, 3) if gen == "tie" else
+         fieldgen.gaussian_field(shape, 6, 7, noise=("uniform", 1e-3)))
+    check_progressive(ctx, dev, f)
+
+
+def test_progressive_gsin256(ctx, dev):
+    f = fieldgen.config_field("gsin256")
+    log("gsin256 progressive, per-level oracle")
+    p = check_progressive(ctx, dev, f)
+    assert p.reclassified[0] == 0
+    assert (p.reclassified[1:] > 0).all()
+    log("reclassified per level", p.reclassified.tolist())
+
+
+def test_progressive_gauss64(ctx, dev):
+    check_progressive(ctx, dev, fieldgen.config_field("gauss64"))
+
+
+def test_determinism(ctx, dev):
+    f = fieldgen.tie_field((40, 50, 70), 1, 2)
+    a = gpu_classify(ctx, dev, f)
+    b = gpu_classify(ctx, dev, f)
+    assert torch.equal(a.codes, b.codes) and torch.equal(a.crit, b.crit)
+
+
+# ---------------------------------------------------------------------------
+# Error paths
+# ---------------------------------------------------------------------------
+def test_nan_reported(ctx, dev):
+    f = fieldgen.iid_field((20, 21, 22), 2)
+    f[5, 6, 7] = np.nan
+    ft = torch.from_numpy(f).to(dev)
+    r = pc.classify(ft, ctx=ctx, check=False)
+    assert r.status == pc.E_NAN
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    pc.classify(ft, ctx=ctx, count_dev=cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == -1
+    # a NaN off the level is not a sample of that level
+    g = fieldgen.iid_field((20, 21, 22), 2)
+    g[5, 6, 7] = np.nan
+    r = pc.classify(torch.from_numpy(g).to(dev), 1, ctx=ctx)
+    assert r.status == 0
+    p = pc.progressive(ft, ctx=ctx, check=False)
+    assert p.status == pc.E_NAN
+
+
+def test_capacity(ctx, dev):
+    f = fieldgen.iid_field((30, 31, 32), 3)
+    ref = oracle.classify(f)
+    ft = torch.from_numpy(f).to(dev)
+    cap = ref.count // 3
+    r = pc.classify(ft, ctx=ctx, capacity=cap, check=False)
+    assert r.status == pc.E_CAPACITY and r.count == ref.count
+    assert np.array_equal(r.crit.cpu().numpy().view(np.uint32), ref.crit[:cap])
+    assert np.array_equal(r.codes.cpu().numpy(), ref.codes)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    pc.classify(ft, ctx=ctx, capacity=cap, count_dev=cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == ref.count
+    p = pc.progressive(ft, ctx=ctx, capacity=10, check=False)
+    assert p.status == pc.E_CAPACITY
+
+
+def test_bad_arguments(ctx, dev):
+    import ctypes
+    lib = pc.binding._load()
+    f = torch.zeros((4, 5, 6), dtype=torch.float32, device=dev)
+    codes = torch.zeros((4, 5, 6), dtype=torch.uint8, device=dev)
+    crit = torch.zeros(200, dtype=torch.int32, device=dev)
+    cnt = ctypes.c_int64(0)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def call(field, nx, ny, nz, level, codes_p, crit_p, cap):
+        return lib.pcrit_classify(ctx.handle, s, field, nx, ny, nz, level,
+                                  codes_p, crit_p, None, cap, ctypes.byref(cnt),
+                                  None)
+    assert call(None, 6, 5, 4, 0, P(codes), P(crit), 200) == pc.E_ARG
+    assert call(P(f), 6, 5, 4, 0, None, P(crit), 200) == pc.E_ARG
+    assert call(P(f), 6, 5, 4, 0, P(codes), None, 200) == pc.E_ARG
+    assert call(ctypes.c_void_p(f.data_ptr() + 2), 6, 5, 4, 0, P(codes), P(crit),
+                200) == pc.E_ARG
+    assert call(P(f), 6, 5, 4, 3, P(codes), P(crit), 200) == pc.E_LEVEL
+    assert call(P(f), 6, 5, 4, -1, P(codes), P(crit), 200) == pc.E_LEVEL
+    assert call(P(f), 1, 5, 4, 0, P(codes), P(crit), 200) == pc.E_DIMS
+    assert call(P(f), 6, 5, 4, 0, P(codes), P(crit), -1) == pc.E_ARG
+    assert call(P(f), 6, 5, 4, 0, P(codes), P(crit), 200) == 0
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads: sampled vertices and invariants
+# ---------------------------------------------------------------------------
+def _sampled_check(f, codes, level, n=20000, seed=0):
+    rng = np.random.default_rng(seed)
+    m = oracle.level_dims(f.shape, level)
+    xs = rng.integers(0, m[0], n)
+    ys = rng.integers(0, m[1], n)
+    zs = rng.integers(0, m[2], n)
+    # include the faces, edges and corners
+    corners = np.array(list(itertools.product(*[(0, mm - 1) for mm in m])))
+    xs = np.concatenate([xs, corners[:, 0]])
+    ys = np.concatenate([ys, corners[:, 1]])
+    zs = np.concatenate([zs, corners[:, 2]])
+    d = oracle.vertex_detail(f, np.stack([xs, ys, zs], 1), level)
+    s = 1 << level
+    if f.ndim == 3:
+        got = codes[zs * s, ys * s, xs * s]
+    else:
+        got = codes[ys * s, xs * s]
+    assert np.array_equal(got, d[:, 0].astype(np.uint8))
+
+
+def _morse_from_codes(codes_t, dim):
+    h = torch.bincount(codes_t.reshape(-1).to(torch.int64), minlength=256).cpu().numpy()
+    c = np.arange(256)
+    nl, nu = c & 7, (c >> 3) & 7
+    if dim == 3:
+        w = (nl == 0).astype(np.int64) - (nu == 0) - np.maximum(nl - 1, 0) + np.maximum(nu - 1, 0)
+    else:
+        w = (nl == 0).astype(np.int64) + (nu == 0) - np.maximum(nl - 1, 0)
+    return int((h * w).sum())
+
+
+@pytest.mark.parametrize("name", ["noisy512", "noisy8192"])
+def test_full_size(ctx, dev, name):
+    """The full-size workloads, every vertex of every level against the
+    oracle (its threaded run takes seconds), direct and progressive."""
+    log("generating", name)
+    f = fieldgen.config_field(name, device="cuda")
+    ft = torch.from_numpy(f).to(dev)
+    log("direct", name)
+    r = pc.classify(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    ref = oracle.classify(f)
+    log("oracle done; critical fraction", ref.count / f.size)
+    assert_same(f, 0, r, ref, name)
+    p = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    assert torch.equal(p.codes, r.codes)
+    crit_all = p.crit.cpu().numpy().view(np.uint32)
+    for i, k in enumerate(p.levels):
+        lref = ref if k == 0 else oracle.classify(f, level=k)
+        assert np.array_equal(crit_all[p.offsets[i]:p.offsets[i + 1]], lref.crit), k
+        if 0 < k <= 2:
+            d = gpu_classify(ctx, dev, f, k)
+            assert_same(f, k, d, lref, f"{name} level {k}")
+    log("reclassified per level", p.reclassified.tolist())
+    del r, p
+    # padded Morse count: with a +inf layer every original vertex is interior
+    log("padded Morse count", name)
+    pad = torch.nn.functional.pad(ft.unsqueeze(0), (1, 1, 1, 1) + ((1, 1) if f.ndim == 3 else ()),
+                                  value=float("inf")).squeeze(0).contiguous()
+    q = pc.classify(pad, ctx=ctx)
+    torch.cuda.synchronize()
+    inner = q.codes[(slice(1, -1),) * f.ndim]
+    assert _morse_from_codes(inner, f.ndim) == 1
+
+
+def test_repeated_direct_is_stable(ctx, dev):
+    """Many z-chunks and blocks in flight: repeated direct passes give the
+    same bytes as the progressive pass (which stages its planes differently)."""
+    f = fieldgen.tie_field((200, 256, 320), 11, 3)
+    ft = torch.from_numpy(f).to(dev)
+    p = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        r = pc.classify(ft, ctx=ctx)
+        torch.cuda.synchronize()
+        assert torch.equal(r.codes, p.codes)
+        assert torch.equal(r.crit, p.level_list(0))

@@ -1,0 +1,154 @@
+"""Host-side checks of the GPU library (no GPU needed).
+
+The library must load and export every function that include/pcrit.h
+declares; its host-built link-pattern table must agree with the oracle's
+explicit-link classification on every polarity pattern; its level geometry
+must agree with the oracle's; and the preview metric must agree with a
+brute-force greedy matching.
+"""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2009_00083_amd as pc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# Bit order of the polarity mask, as documented in include/pcrit.h.
+OFF3 = [(0, 0, -1), (-1, 0, -1), (0, -1, -1), (-1, -1, -1),
+        (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (-1, -1, 0), (1, 1, 0),
+        (0, 0, 1), (1, 0, 1), (0, 1, 1), (1, 1, 1)]
+OFF2 = [(-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, 1)]
+
+
+def test_library_exports_header_symbols():
+    import ctypes
+    hdr = open(os.path.join(ROOT, "include", "pcrit.h")).read()
+    declared = set(re.findall(r"\b(pcrit_[a-z0-9_]+)\s*\(", hdr))
+    declared.discard("pcrit_level_cb")
+    assert declared == set(pc.binding.EXPORTED)
+    lib = ctypes.CDLL(pc.library_path())
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+
+
+def test_header_documents_bit_order():
+    hdr = open(os.path.join(ROOT, "include", "pcrit.h")).read()
+    part = hdr.split("14 offsets in the order", 1)[1]
+    listed = re.findall(r"\((-?\d),(-?\d),(-?\d)\)", part)
+    three = [tuple(int(v) for v in t) for t in listed]
+    assert three[:14] == OFF3
+
+
+def _packed_patterns(offsets, dim):
+    """Disjoint 3^dim blocks, one per mask: centre 0, neighbour j = +1 if bit
+    j is set (after the centre) else -1."""
+    n = 1 << len(offsets)
+    if dim == 3:
+        bx, by, bz = 32, 32, n // 1024
+        f = np.full((3 * bz, 3 * by, 3 * bx), 0.25, np.float32)
+        centres = []
+        for b in range(n):
+            cx, cy, cz = 3 * (b % bx) + 1, 3 * ((b // bx) % by) + 1, 3 * (b // (bx * by)) + 1
+            f[cz, cy, cx] = 0.0
+            for j, (dx, dy, dz) in enumerate(offsets):
+                f[cz + dz, cy + dy, cx + dx] = 1.0 if (b >> j) & 1 else -1.0
+            centres.append((cx, cy, cz))
+        return f, np.array(centres)
+    bx = 8
+    f = np.full((3 * (n // bx), 3 * bx), 0.25, np.float32)
+    centres = []
+    for b in range(n):
+        cx, cy = 3 * (b % bx) + 1, 3 * (b // bx) + 1
+        f[cy, cx] = 0.0
+        for j, (dx, dy) in enumerate(offsets):
+            f[cy + dy, cx + dx] = 1.0 if (b >> j) & 1 else -1.0
+        centres.append((cx, cy, 0))
+    return f, np.array(centres)
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_link_table_matches_oracle(oracle_mod, dim):
+    """Table entry for mask m == (lower, upper) component counts of the
+    oracle for a vertex whose neighbours follow m."""
+    offsets = OFF3 if dim == 3 else OFF2
+    table = pc.link_table(dim)
+    f, centres = _packed_patterns(offsets, dim)
+    d = oracle_mod.vertex_detail(f, centres)
+    assert np.array_equal(table & 7, d[:, 1])
+    assert np.array_equal(table >> 3, d[:, 2])
+
+
+@pytest.mark.parametrize("shape", [(512, 512, 512), (256, 256, 256), (64, 64, 64),
+                                   (8192, 8192), (33, 17, 9), (2, 2, 2), (5, 3),
+                                   (100, 2, 7)])
+def test_level_geometry_matches_oracle(oracle_mod, shape):
+    k = pc.max_level(shape)
+    assert k == oracle_mod.max_level(shape)
+    for level in range(k + 1):
+        assert pc.level_dims(shape, level) == oracle_mod.level_dims(shape, level)
+    with pytest.raises(pc.PcritError) as e:
+        pc.level_dims(shape, k + 1)
+    assert e.value.status == pc.E_LEVEL
+
+
+def test_bad_dims_rejected():
+    for shape in [(5, 5, 1), (5, 1, 5), (4, 1), (1, 7), (1 << 17, 1 << 16, 2)]:
+        with pytest.raises(pc.PcritError) as e:
+            pc.max_level(shape)
+        assert e.value.status == pc.E_DIMS
+
+
+def _greedy_f1(shape, level, p, pcode, e, ecode):
+    """Brute force: list every candidate pair, sort by (distance, p, e),
+    take greedily."""
+    nz, ny, nx = shape if len(shape) == 3 else (1,) + tuple(shape)
+    D = 1 << level
+
+    def xyz(i):
+        return i % nx, (i // nx) % ny, i // (nx * ny)
+
+    def typ(c):
+        nl, nu = c & 7, (c >> 3) & 7
+        return 1 if nl == 0 else 2 if nu == 0 else 3
+
+    pairs = []
+    for a, ca in zip(p, pcode):
+        for b, cb in zip(e, ecode):
+            if typ(ca) != typ(cb):
+                continue
+            d = max(abs(u - v) for u, v in zip(xyz(int(a)), xyz(int(b))))
+            if d <= D:
+                pairs.append((d, int(a), int(b)))
+    pairs.sort()
+    used_p, used_e, m = set(), set(), 0
+    for d, a, b in pairs:
+        if a in used_p or b in used_e:
+            continue
+        used_p.add(a)
+        used_e.add(b)
+        m += 1
+    tot = len(p) + len(e)
+    return (2.0 * m / tot if tot else 1.0), m
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_preview_f1_matches_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    shape = [(9, 10, 11), (13, 12), (6, 7, 5), (40, 3)][seed % 4]
+    n = int(np.prod(shape))
+    level = int(rng.integers(0, 3))
+    e = np.sort(rng.choice(n, size=int(rng.integers(0, n // 3 + 1)), replace=False))
+    p = np.sort(rng.choice(n, size=int(rng.integers(0, n // 8 + 1)), replace=False))
+    codes = np.array([0b000001, 0b001000, 0b010001, 0b001010, 0b011010],
+                     np.uint8)  # min, max, saddles
+    ec = codes[rng.integers(0, 5, size=len(e))]
+    pcd = codes[rng.integers(0, 5, size=len(p))]
+    f1, m = pc.preview_f1(shape, level, p.astype(np.uint32), pcd,
+                          e.astype(np.uint32), ec)
+    f1b, mb = _greedy_f1(shape, level, p, pcd, e, ec)
+    assert m == mb
+    assert f1 == pytest.approx(f1b)
