@@ -72,10 +72,13 @@ struct pcrit_ctx {
   uint8_t *lut3 = nullptr, *lut2 = nullptr;
   uint64_t *bits[2] = {nullptr, nullptr};
   int64_t bits_words = 0;
-  uint64_t *lb = nullptr;
-  int64_t lb_n = 0;
-  // flags[0] nan, [1] error, [2] look-back counter, [3 + i] re-classified
-  // old vertices of progressive step i
+  int *counts = nullptr;  // per-chunk critical counts of the compaction
+  int64_t counts_n = 0;
+  void *masks[2] = {nullptr, nullptr};  // polarity masks, level ping-pong
+  int64_t masks_bytes = 0;
+  unsigned *reclass_part = nullptr;  // per-block counts of a progressive level
+  int reclass_n = 0;
+  // flags[0] nan, [3 + i] re-classified old vertices of progressive step i
   unsigned *flags = nullptr;
   int64_t *level_base = nullptr;  // kMaxLevels + 2 entries, [0] stays 0
   // pinned host mirror for read-back
@@ -96,6 +99,20 @@ constexpr int kFlagWords = 3 + kMaxLevels + 2;
 
 int hip_status(hipError_t e) { return e == hipSuccess ? PCRIT_OK : PCRIT_E_HIP; }
 
+int ensure_masks(pcrit_ctx *c, int64_t bytes) {
+  if (bytes <= c->masks_bytes) return PCRIT_OK;
+  hipDeviceSynchronize();
+  for (int i = 0; i < 2; i++) {
+    if (c->masks[i]) hipFree(c->masks[i]);
+    c->masks[i] = nullptr;
+  }
+  c->masks_bytes = 0;
+  for (int i = 0; i < 2; i++)
+    if (hipMalloc(&c->masks[i], (size_t)bytes) != hipSuccess) return PCRIT_E_OOM;
+  c->masks_bytes = bytes;
+  return PCRIT_OK;
+}
+
 int ensure_scratch(pcrit_ctx *c, int64_t words, int64_t chunks) {
   if (words > c->bits_words) {
     hipDeviceSynchronize();
@@ -109,13 +126,14 @@ int ensure_scratch(pcrit_ctx *c, int64_t words, int64_t chunks) {
         return PCRIT_E_OOM;
     c->bits_words = words;
   }
-  if (chunks > c->lb_n) {
+  if (chunks > c->counts_n) {
     hipDeviceSynchronize();
-    if (c->lb) hipFree(c->lb);
-    c->lb = nullptr;
-    c->lb_n = 0;
-    if (hipMalloc(&c->lb, (size_t)chunks * 8) != hipSuccess) return PCRIT_E_OOM;
-    c->lb_n = chunks;
+    if (c->counts) hipFree(c->counts);
+    c->counts = nullptr;
+    c->counts_n = 0;
+    if (hipMalloc(&c->counts, (size_t)chunks * sizeof(int)) != hipSuccess)
+      return PCRIT_E_OOM;
+    c->counts_n = chunks;
   }
   return PCRIT_OK;
 }
@@ -135,12 +153,15 @@ void record_kernel(pcrit_ctx *c, int which, int level, int end, hipStream_t st) 
 }
 
 // Enqueue classification (+ compaction) of one level.
+// Progressive steps: prev != null reads the polarity masks of the previous
+// (coarser) level from masks[mask_slot ^ 1]; write_masks stores this level's
+// masks into masks[mask_slot] for the next level.
 int enqueue_level(pcrit_ctx *c, hipStream_t st, const float *field,
-                  const Geom &g, bool progressive, const Geom *prev,
-                  int bits_out, uint8_t *codes, uint32_t *crit,
+                  const Geom &g, const Geom *prev, bool write_masks,
+                  int bits_out, int mask_slot, uint8_t *codes, uint32_t *crit,
                   uint8_t *crit_codes, int64_t cap, int slot,
-                  int64_t *count_dev, unsigned gen, unsigned *reclass,
-                  unsigned *zero_next) {
+                  int64_t *count_dev, unsigned gen, unsigned *reclass) {
+  const bool progressive = prev != nullptr;
   const int64_t chunks = (g.words + kChunkWords - 1) / kChunkWords;
   ClassifyArgs a{};
   a.f = field;
@@ -155,29 +176,21 @@ int enqueue_level(pcrit_ctx *c, hipStream_t st, const float *field,
   a.mz = (int)g.mz;
   a.rowwords = (int)g.rowwords;
   if (progressive) {
-    a.prev_bits = c->bits[bits_out ^ 1];
-    a.prev_rowwords = (int)prev->rowwords;
-    a.prev_my = (int)prev->my;
-    a.reclass = reclass;
+    a.prev_masks = c->masks[mask_slot ^ 1];
+    a.pmx = (int)prev->mx;
+    a.pmy = (int)prev->my;
   }
+  if (write_masks) a.masks = c->masks[mask_slot];
+  a.reclass_part = c->reclass_part;
   a.nan_flag = &c->flags[0];
   a.gen = gen;
-  a.lb_state = c->lb;
-  a.lb_n = (int)chunks;
-  a.lb_counter = &c->flags[2];
   hipError_t e;
+  int grid = 0;
   record_kernel(c, 0, g.level, 0, st);
-  if (g.dim == 3) {
-    a.zchunk = classify3d_zchunk(a.mx, a.my, a.mz);
-    a.ntx = (a.mx + kTile3X - 1) / kTile3X;
-    a.nty = (a.my + kTile3Y - 1) / kTile3Y;
-    e = launch_classify3d(a, progressive, st);
-  } else {
-    a.zchunk = classify2d_ychunk(a.mx, a.my);
-    a.ntx = (a.mx + kTile2X - 1) / kTile2X;
-    a.nty = 1;
-    e = launch_classify2d(a, progressive, st);
-  }
+  if (g.dim == 3)
+    e = launch_classify3d(a, progressive, write_masks, st, &grid);
+  else
+    e = launch_classify2d(a, progressive, write_masks, st, &grid);
   if (e != hipSuccess) return PCRIT_E_HIP;
   record_kernel(c, 0, g.level, 1, st);
 
@@ -197,12 +210,14 @@ int enqueue_level(pcrit_ctx *c, hipStream_t st, const float *field,
   b.slot = slot;
   b.count_dev = count_dev;
   b.nan_flag = &c->flags[0];
-  b.err_flag = &c->flags[1];
   b.gen = gen;
-  b.lb_state = c->lb;
-  b.lb_counter = &c->flags[2];
+  b.counts = c->counts;
   b.nchunks = (int)chunks;
-  b.zero_next = zero_next;
+  if (progressive) {
+    b.reclass_part = c->reclass_part;
+    b.reclass_n = std::min(grid, c->reclass_n);
+    b.reclass_out = reclass;
+  }
   record_kernel(c, 1, g.level, 0, st);
   e = launch_compact(b, st);
   if (e != hipSuccess) return PCRIT_E_HIP;
@@ -276,6 +291,7 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   if (hipSetDevice(hip_device) != hipSuccess) return PCRIT_E_HIP;
   pcrit_ctx *c = new pcrit_ctx();
   c->device = hip_device;
+  c->reclass_n = classify_max_blocks();
   uint8_t h3[kLut3Size], h2[kLut2Size];
   build_link_table3(h3);
   build_link_table2(h2);
@@ -283,6 +299,8 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
             hipMalloc(&c->lut2, kLut2Size) == hipSuccess &&
             hipMalloc(&c->flags, kFlagWords * sizeof(unsigned)) == hipSuccess &&
             hipMalloc(&c->level_base, (kMaxLevels + 2) * sizeof(int64_t)) ==
+                hipSuccess &&
+            hipMalloc(&c->reclass_part, classify_max_blocks() * sizeof(unsigned)) ==
                 hipSuccess &&
             hipHostMalloc(&c->h_base, (kMaxLevels + 2) * sizeof(int64_t)) ==
                 hipSuccess &&
@@ -312,7 +330,10 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->lut2);
   hipFree(c->bits[0]);
   hipFree(c->bits[1]);
-  hipFree(c->lb);
+  hipFree(c->counts);
+  hipFree(c->masks[0]);
+  hipFree(c->masks[1]);
+  hipFree(c->reclass_part);
   hipFree(c->flags);
   hipFree(c->level_base);
   if (c->h_base) hipHostFree(c->h_base);
@@ -347,9 +368,9 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
   if (st) return st;
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
-  st = enqueue_level(c, s, field, g, false, nullptr, 0, codes, crit,
+  st = enqueue_level(c, s, field, g, nullptr, false, 0, 0, codes, crit,
                      crit_codes, crit_capacity, 0, crit_count_dev, gen,
-                     nullptr, nullptr);
+                     nullptr);
   if (st) return st;
   if (!crit_count_host) return PCRIT_OK;
   if (hipMemcpyAsync(c->h_base, c->level_base, 2 * sizeof(int64_t),
@@ -360,7 +381,6 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
     return PCRIT_E_HIP;
   const int64_t count = c->h_base[1] - c->h_base[0];
   *crit_count_host = count;
-  if (c->h_flags[1] == gen) return PCRIT_E_HIP;
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
   return count > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
@@ -390,16 +410,20 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   for (int k = 0; k <= kmax; k++) max_words = std::max(max_words, geo[k].words);
   st = ensure_scratch(c, max_words, (max_words + kChunkWords - 1) / kChunkWords);
   if (st) return st;
+  if (kmax > 0) {
+    // masks of levels kmax .. 1 (the finest of them is the largest)
+    const Geom &g1 = geo[1];
+    st = ensure_masks(c, g1.mx * g1.my * g1.mz * (g1.dim == 3 ? 2 : 1));
+    if (st) return st;
+  }
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
   if (hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
   for (int i = 0; i <= kmax; i++) {
     const int k = kmax - i;
-    unsigned *reclass = &c->flags[3 + i];
-    unsigned *zero_next = &c->flags[3 + i + 1];
-    st = enqueue_level(c, s, field, geo[k], i > 0, i > 0 ? &geo[k + 1] : nullptr,
-                       i & 1, codes, crit, crit_codes, crit_capacity, i,
-                       nullptr, gen, reclass, zero_next);
+    st = enqueue_level(c, s, field, geo[k], i > 0 ? &geo[k + 1] : nullptr,
+                       k > 0, i & 1, i & 1, codes, crit, crit_codes,
+                       crit_capacity, i, nullptr, gen, &c->flags[3 + i]);
     if (st) return st;
     if (hipEventRecord(c->ev_level[i], s) != hipSuccess) return PCRIT_E_HIP;
     if (cb) {
@@ -428,7 +452,6 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
         ms = -1.f;
       level_ms_host[i] = ms;
     }
-  if (c->h_flags[1] == gen) return PCRIT_E_HIP;
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
   return c->h_base[kmax + 1] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }

@@ -1,20 +1,13 @@
 // Classification and compaction kernels for gfx950 (MI355X).
 //
-// classify3d: one block = 64 (x) x kTile3Y (y) vertex columns of a level grid,
-// marching along z over `zchunk` planes.  Each plane of the tile, plus a halo
-// of H samples, is read from HBM once into an LDS ring; every thread keeps the
-// 7-point in-plane stencil (centre, +-x, +-y, +(1,1), -(1,1)) of the planes
-// z-1, z, z+1 in registers, so a vertex costs 7 LDS reads instead of 15.  The
-// 14 neighbour comparisons form the polarity mask, one byte of the
-// link-pattern table (staged in LDS) gives the lower/upper link component
-// counts, and boundary vertices take a second lookup with their off-grid
-// neighbours forced to one side.  Critical flags leave the block as one
-// 64-bit ballot word per wave row.
+// classify3d / classify2d: per-vertex critical-point classification of one
+// level of the hierarchy (wave tiles marched along the slowest axis, see
+// below); the result per vertex is a code byte and a bit of the level's
+// critical bitmask.
 //
-// compact: turns the per-level critical bitmask into the ascending list of
-// full-resolution indices: a single pass with decoupled look-back over
-// chunks whose ids are handed out in start order, then a wave-cooperative
-// expansion in which every store instruction writes consecutive entries.
+// count/expand: turn the per-level critical bitmask into the ascending list
+// of full-resolution indices; the expansion is wave-cooperative, so every
+// store instruction writes consecutive list entries.
 #include "pcrit_internal.h"
 
 namespace pcrit {
@@ -102,371 +95,509 @@ constexpr unsigned AXM2 = side_mask2(0, -1), AXP2 = side_mask2(0, 1);
 constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 
 // ---------------------------------------------------------------------------
+// Shared structure of the classification kernels
+// ---------------------------------------------------------------------------
+// * Every wave owns a tile: 64 consecutive x (one sample per lane) by R rows
+//   (3D) or one row (2D), marched along the slowest axis.  The waves of a
+//   block share only the link-pattern table, so there is no block barrier
+//   inside the march.
+// * The samples of a plane stay in registers.  The x-1 and x+1 neighbours
+//   come from the lanes next door through DPP wave shifts; lanes 0 and 63
+//   take them from a halo load of the same row.
+// * A polarity bit is the sign of one float difference, appended to the mask
+//   with one alignbit.  For a centre c that is finite and non-zero the sign
+//   of c - n (or n - c) is exact, ties included; lanes whose centre is +-0,
+//   +-inf or NaN take exact comparisons instead.
+// * The march issues global loads only (planes kept three ahead).  On this
+//   architecture loads and stores share one completion counter, and with a
+//   store in flight the compiler can no longer wait for one particular load;
+//   codes and masks are therefore staged in LDS and written after the tile.
+// * Persistent blocks walk the tile list; the tiles of one XCD form a
+//   contiguous run, so neighbouring tiles (which share halo rows) meet in
+//   the same L2.
+constexpr int kUnroll = 6;       // march unroll: window period 3, parity 2
+constexpr uint8_t kKeep = 0xFF;  // staging: no code to write (never a code)
+constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- lane i reads lane i-1
+constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
+constexpr unsigned kPos3 = 0x3EA0u;  // mask bits of positive 3D offsets
+constexpr unsigned kPos2 = 0x2Au;    // mask bits of positive 2D offsets
+
+// x-1 neighbour: lane i gets lane i-1, lane 0 gets `halo` (its lane-0 value)
+__device__ __forceinline__ float from_left(float halo, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(
+      __float_as_int(halo), __float_as_int(v), kDppShr1, 0xF, 0xF, false));
+}
+// x+1 neighbour: lane i gets lane i+1, lane 63 gets `halo` (its lane-63 value)
+__device__ __forceinline__ float from_right(float halo, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(
+      __float_as_int(halo), __float_as_int(v), kDppShl1, 0xF, 0xF, false));
+}
+// m << 1 | sign bit of d
+__device__ __forceinline__ unsigned push_sign(unsigned m, float d) {
+  return __builtin_amdgcn_alignbit(m, __float_as_uint(d), 31);
+}
+// +-0, +-inf, NaN: the centres whose differences may not carry the order
+__device__ __forceinline__ bool special_centre(float c) {
+  return __builtin_amdgcn_class(c, 0x3 | 0x4 | 0x200 | 0x20 | 0x40);
+}
+
+// One plane of a wave tile: rows y0-1 .. y0+R (index i = row - y0 + 1).
+template <int R>
+struct Plane {
+  float v[R + 2];  // samples at x
+  float l[R + 2];  // samples at x-1 (rows 0..R used)
+  float r[R + 2];  // samples at x+1 (rows 1..R+1 used)
+  unsigned pm;     // previous-level masks of the even rows (progressive)
+};
+
+template <int R>
+struct PlaneLoad {
+  float v[R + 2];
+  float h[R + 2];  // lane 0: x0-1, lane 63: x0+64, other lanes: x again
+  unsigned pm[(R + 1) / 2];
+};
+
+// ---------------------------------------------------------------------------
 // 3D classification
 // ---------------------------------------------------------------------------
-template <int TY, int H, bool PROG>
-__global__ __launch_bounds__(64 * TY) void classify3d_kernel(ClassifyArgs a) {
-  constexpr int NT = 64 * TY;
-  constexpr int TXH = 64 + 2 * H;      // LDS row pitch (floats)
-  constexpr int TYH = TY + 2 * H;      // rows per LDS plane
-  constexpr int PLANE = TXH * TYH;
-  // Planes in the LDS ring.  Step z reads planes z-H .. z+H (the progressive
-  // path reaches two planes out) and stores plane z+H+1; the slot it stores
-  // into must not be one that a slower wave may still read before the next
-  // barrier, including the prologue's reads of planes z0-1 and z0, hence at
-  // least 2H+2 slots.
-  constexpr int NS = 2 * H + 2;
-  constexpr int RPW = (TYH + TY - 1) / TY;  // plane rows loaded per wave
-  __shared__ float sp[NS * PLANE];
+template <int R, bool RP, bool WM>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
+    ClassifyArgs a) {
+  constexpr int NW = kWavesPerBlock;
+  constexpr int NR = R + 2;
+  constexpr int ZC = kZChunk3;
+  constexpr int U = kUnroll;
+  static_assert(ZC % U == 0, "tile depth must be a multiple of the unroll");
+  static_assert(ZC * R <= 64, "one critical word per lane");
+  static_assert(R % 2 == 0, "tiles start on even rows");
   __shared__ __attribute__((aligned(16))) uint8_t slut[kLut3Size];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][ZC * R * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? ZC * R * 64 : 2];
   __shared__ unsigned s_reclass;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int id = xcd_block_id();
-  const int tx = id % a.ntx, rest = id / a.ntx;
-  const int ty = rest % a.nty, zc = rest / a.nty;
-  const int x0 = tx * 64, y0 = ty * TY, z0 = zc * a.zchunk;
-  const int z1 = min(z0 + a.zchunk, a.mz);
-
-  // Clear the look-back state of the compaction launched after this kernel.
-  for (int i = id * NT + tid; i < a.lb_n; i += (int)gridDim.x * NT)
-    a.lb_state[i] = 0ull;
-  if (id == 0 && tid == 0) *a.lb_counter = 0u;
-  if (PROG && tid == 0) s_reclass = 0u;
   {
     const uint4 *g = reinterpret_cast<const uint4 *>(a.lut);
     uint4 *s = reinterpret_cast<uint4 *>(slut);
-    for (int i = tid; i < kLut3Size / 16; i += NT) s[i] = g[i];
+    for (int i = tid; i < kLut3Size / 16; i += 64 * NW) s[i] = g[i];
   }
-
-  // Plane loader: wave w fetches tile rows w, w+TY, ...; per row the 64
-  // lanes read the tile interior (one 256-byte run at stride 1) and lanes
-  // 0..2H-1 the halo columns.  Off-grid samples are never read.
-  auto load_plane = [&](int z, float (&v)[RPW][2]) {
-#pragma unroll
-    for (int k = 0; k < RPW; k++) {
-      v[k][0] = 0.f;
-      v[k][1] = 0.f;
-      const int r = w + k * TY;
-      const int y = y0 - H + r;
-      if (r < TYH && z >= 0 && z < a.mz && y >= 0 && y < a.my) {
-        const float *row = a.f + (int64_t)z * a.sz + (int64_t)y * a.sy;
-        const int x = x0 + lane;
-        if (x < a.mx) v[k][0] = row[(int64_t)x * a.sx];
-        if (lane < 2 * H) {
-          const int c = lane < H ? lane : 64 + lane;
-          const int xh = x0 - H + c;
-          if (xh >= 0 && xh < a.mx) v[k][1] = row[(int64_t)xh * a.sx];
-        }
-      }
-    }
-  };
-  auto store_plane = [&](int slot, const float (&v)[RPW][2]) {
-    float *pl = sp + slot * PLANE;
-#pragma unroll
-    for (int k = 0; k < RPW; k++) {
-      const int r = w + k * TY;
-      if (r < TYH) {
-        pl[r * TXH + H + lane] = v[k][0];
-        if (lane < 2 * H) pl[r * TXH + (lane < H ? lane : 64 + lane)] = v[k][1];
-      }
-    }
-  };
-  const int cbase = (w + H) * TXH + H + lane;  // this thread's column
-  // in-plane stencil: (0,0) (-1,0) (1,0) (0,-1) (0,1) (-1,-1) (1,1)
-  auto stencil = [&](int slot, float (&P)[7]) {
-    const float *q = sp + slot * PLANE + cbase;
-    P[0] = q[0];
-    P[1] = q[-1];
-    P[2] = q[1];
-    P[3] = q[-TXH];
-    P[4] = q[TXH];
-    P[5] = q[-TXH - 1];
-    P[6] = q[TXH + 1];
-  };
-  auto slot_of = [&](int z) { return (z - z0 + H) % NS; };
-
-  // Prologue: planes z0-H .. z0+H into the ring, two more in flight.
-  {
-    float pro[2 * H + 1][RPW][2];
-#pragma unroll
-    for (int i = 0; i < 2 * H + 1; i++) load_plane(z0 - H + i, pro[i]);
-#pragma unroll
-    for (int i = 0; i < 2 * H + 1; i++) store_plane(i, pro[i]);
-  }
-  float pfA[RPW][2], pfB[RPW][2];
-  load_plane(z0 + H + 1, pfA);
-  load_plane(z0 + H + 2, pfB);
+  if (tid == 0) s_reclass = 0u;
   __syncthreads();
-  float P0[7], P1[7], P2[7];
-  stencil(slot_of(z0 - 1), P0);
-  stencil(slot_of(z0), P1);
 
-  const int x = x0 + lane, y = y0 + w;
-  const bool col_active = (x < a.mx) && (y < a.my);
-  const int64_t col_off = (int64_t)y * a.sy + (int64_t)x * a.sx;
-  uint64_t *bits_row = a.bits + (int64_t)y * a.rowwords + (x0 >> 6);
-  const int64_t bits_plane = (int64_t)a.my * a.rowwords;
+  bool nan_seen = false;
+  unsigned reclass = 0;  // wave-uniform
+  const int nwaves = (int)gridDim.x * NW;
+  const uint16_t *pmasks = reinterpret_cast<const uint16_t *>(a.prev_masks);
+  uint16_t *omasks = reinterpret_cast<uint16_t *>(a.masks);
 
-  for (int z = z0; z < z1; z++) {
-    stencil(slot_of(z + 1), P2);
-    const float c = P1[0];
-    const float lo[4] = {P0[0], P0[1], P0[3], P0[5]};
-    const float mid[6] = {P1[1], P1[2], P1[3], P1[4], P1[5], P1[6]};
-    const float hi[4] = {P2[0], P2[2], P2[4], P2[6]};
-    const unsigned m = mask3(c, lo, mid, hi);
-    if (col_active && c != c) *a.nan_flag = a.gen;
+  for (int t = xcd_block_id() * NW + w; t < a.ntiles; t += nwaves) {
+    const int tx = t % a.ntx, rest = t / a.ntx;
+    const int ty = rest % a.nty, zc = rest / a.nty;
+    const int x0 = tx * 64, y0 = ty * R, z0 = zc * ZC;
+    const int z1 = min(z0 + ZC, a.mz);
+    const int x = x0 + lane;
+    const bool col = x < a.mx;
 
-    // absent neighbours (only waves that touch the level boundary)
-    const bool wave_inner = y > 0 && y < a.my - 1 && z > 0 && z < a.mz - 1 &&
-                            x0 > 0 && x0 + 64 < a.mx;
-    unsigned A = 0;
-    if (!wave_inner) {
-      A = (x == 0 ? AXM3 : 0u) | (x == a.mx - 1 ? AXP3 : 0u) |
-          (y == 0 ? AYM3 : 0u) | (y == a.my - 1 ? AYP3 : 0u) |
-          (z == 0 ? AZM3 : 0u) | (z == a.mz - 1 ? AZP3 : 0u);
-    }
+    // Clamped, unconditional loads (a clamped sample is never used: the
+    // absent-neighbour mask covers every off-grid position).
+    const int xc = min(x, a.mx - 1);
+    const int xh = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + 64, a.mx - 1) : xc);
+    const int64_t xoff = (int64_t)xc * a.sx, hoff = (int64_t)xh * a.sx;
+    int64_t yoff[NR];
+#pragma unroll
+    for (int i = 0; i < NR; i++)
+      yoff[i] = (int64_t)min(max(y0 - 1 + i, 0), a.my - 1) * a.sy;
+    // previous-level mask of (x/2, y/2, z/2) for the even rows
+    const int pxc = min(xc >> 1, a.pmx - 1);
 
-    bool need = col_active;
-    bool old_dirty = false;
-    bool crit = false;
-    if (PROG) {
-      const bool old = col_active && !((x | y | z) & 1);
-      if (old) {
-        // Level-(k+1) neighbours of an old vertex sit two level-k steps
-        // away; its level-(k+1) mask uses them, with the same tie rule.
-        const float *qm = sp + slot_of(z - 2) * PLANE + cbase;
-        const float *q0 = sp + slot_of(z) * PLANE + cbase;
-        const float *qp = sp + slot_of(z + 2) * PLANE + cbase;
-        const float flo[4] = {qm[0], qm[-2], qm[-2 * TXH], qm[-2 * TXH - 2]};
-        const float fmid[6] = {q0[-2],       q0[2],       q0[-2 * TXH],
-                               q0[2 * TXH],  q0[-2 * TXH - 2],
-                               q0[2 * TXH + 2]};
-        const float fhi[4] = {qp[0], qp[2], qp[2 * TXH], qp[2 * TXH + 2]};
-        const unsigned m2 = mask3(c, flo, fmid, fhi);
-        // absent at level k+1: beyond the last even coordinate
-        const int ex = 2 * ((a.mx - 1) >> 1), ey = 2 * ((a.my - 1) >> 1),
-                  ez = 2 * ((a.mz - 1) >> 1);
-        const unsigned Afull =
-            (x == 0 ? AXM3 : 0u) | (x == a.mx - 1 ? AXP3 : 0u) |
-            (y == 0 ? AYM3 : 0u) | (y == a.my - 1 ? AYP3 : 0u) |
-            (z == 0 ? AZM3 : 0u) | (z == a.mz - 1 ? AZP3 : 0u);
-        const unsigned A2 = (x == 0 ? AXM3 : 0u) | (x == ex ? AXP3 : 0u) |
-                            (y == 0 ? AYM3 : 0u) | (y == ey ? AYP3 : 0u) |
-                            (z == 0 ? AZM3 : 0u) | (z == ez ? AZP3 : 0u);
-        old_dirty = (A2 != Afull) || (((m ^ m2) & ~Afull & 0x3FFFu) != 0u);
-        if (!old_dirty) {
-          // unchanged: keep the code and the critical status of level k+1
-          need = false;
-          const int xp = x >> 1, yp = y >> 1, zp = z >> 1;
-          const uint64_t wb =
-              a.prev_bits[((int64_t)zp * a.prev_my + yp) * a.prev_rowwords +
-                          (xp >> 6)];
-          crit = (wb >> (xp & 63)) & 1ull;
+    auto load = [&](int z, PlaneLoad<R> &d) {
+      const int zcl = min(max(z, 0), a.mz - 1);
+      const float *pl = a.f + (int64_t)zcl * a.sz;
+#pragma unroll
+      for (int i = 0; i < NR; i++) {
+        d.v[i] = pl[yoff[i] + xoff];
+        d.h[i] = pl[yoff[i] + hoff];
+      }
+      if (RP) {
+        const int pz = zcl >> 1;
+#pragma unroll
+        for (int k = 0; k < (R + 1) / 2; k++) {
+          const int py = min((y0 + 2 * k) >> 1, a.pmy - 1);
+          d.pm[k] = pmasks[((int64_t)pz * a.pmy + py) * a.pmx + pxc];
         }
       }
+    };
+    auto derive = [&](const PlaneLoad<R> &d, Plane<R> &p) {
+#pragma unroll
+      for (int i = 0; i < NR; i++) p.v[i] = d.v[i];
+#pragma unroll
+      for (int i = 0; i <= R; i++) p.l[i] = from_left(d.h[i], d.v[i]);
+#pragma unroll
+      for (int i = 1; i <= R + 1; i++) p.r[i] = from_right(d.h[i], d.v[i]);
+      if (RP) {
+        unsigned pm = 0;
+#pragma unroll
+        for (int k = 0; k < (R + 1) / 2; k++) pm |= d.pm[k] << (16 * k);
+        p.pm = pm;
+      }
+    };
+
+    uint64_t wbits = 0;  // lane q holds the critical word of staged row q
+    uint8_t *stc = scode[w];
+    uint16_t *stm = smask[WM ? w : 0];
+
+    // Classify the R vertices of plane z in this lane's column.
+    auto step = [&](int z, const Plane<R> &lo, const Plane<R> &mid,
+                    const Plane<R> &hi) {
+      const bool zlive = z < z1;
+#pragma unroll
+      for (int j = 0; j < R; j++) {
+        const int i = j + 1;
+        const int y = y0 + j;
+        const bool live = zlive && col && y < a.my;
+        const float c = mid.v[i];
+        unsigned m = 0;
+        m = push_sign(m, hi.r[i + 1] - c);   // 13 (1,1,1)
+        m = push_sign(m, hi.v[i + 1] - c);   // 12 (0,1,1)
+        m = push_sign(m, hi.r[i] - c);       // 11 (1,0,1)
+        m = push_sign(m, hi.v[i] - c);       // 10 (0,0,1)
+        m = push_sign(m, mid.r[i + 1] - c);  //  9 (1,1,0)
+        m = push_sign(m, c - mid.l[i - 1]);  //  8 (-1,-1,0)
+        m = push_sign(m, mid.v[i + 1] - c);  //  7 (0,1,0)
+        m = push_sign(m, c - mid.v[i - 1]);  //  6 (0,-1,0)
+        m = push_sign(m, mid.r[i] - c);      //  5 (1,0,0)
+        m = push_sign(m, c - mid.l[i]);      //  4 (-1,0,0)
+        m = push_sign(m, c - lo.l[i - 1]);   //  3 (-1,-1,-1)
+        m = push_sign(m, c - lo.v[i - 1]);   //  2 (0,-1,-1)
+        m = push_sign(m, c - lo.l[i]);       //  1 (-1,0,-1)
+        m = push_sign(m, c - lo.v[i]);       //  0 (0,0,-1)
+        m ^= kPos3;
+        if (special_centre(c)) {
+          const float lov[4] = {lo.v[i], lo.l[i], lo.v[i - 1], lo.l[i - 1]};
+          const float midv[6] = {mid.l[i],     mid.r[i],     mid.v[i - 1],
+                                 mid.v[i + 1], mid.l[i - 1], mid.r[i + 1]};
+          const float hiv[4] = {hi.v[i], hi.r[i], hi.v[i + 1], hi.r[i + 1]};
+          m = mask3(c, lov, midv, hiv);
+          nan_seen |= live && (c != c);
+        }
+        // absent neighbours, only in waves that touch the level boundary
+        const bool inner = y > 0 && y < a.my - 1 && z > 0 && z < a.mz - 1 &&
+                           x0 > 0 && x0 + 64 < a.mx;
+        unsigned A = 0;
+        if (!inner)
+          A = (x == 0 ? AXM3 : 0u) | (x == a.mx - 1 ? AXP3 : 0u) |
+              (y == 0 ? AYM3 : 0u) | (y == a.my - 1 ? AYP3 : 0u) |
+              (z == 0 ? AZM3 : 0u) | (z == a.mz - 1 ? AZP3 : 0u);
+        const unsigned code = A == 0u ? (unsigned)slut[m] : boundary_code3(slut, m, A);
+        uint8_t out = live ? (uint8_t)code : kKeep;
+        if (RP && !(j & 1) && !(z & 1)) {
+          // old vertex (present at level k+1): re-classified only if its
+          // polarity mask or its set of absent neighbours changed
+          const bool old = live && !(x & 1);
+          const unsigned pm = (mid.pm >> (16 * (j >> 1))) & 0xFFFFu;
+          const int ex = 2 * ((a.mx - 1) >> 1), ey = 2 * ((a.my - 1) >> 1),
+                    ez = 2 * ((a.mz - 1) >> 1);
+          const unsigned Af =
+              (x == 0 ? AXM3 : 0u) | (x == a.mx - 1 ? AXP3 : 0u) |
+              (y == 0 ? AYM3 : 0u) | (y == a.my - 1 ? AYP3 : 0u) |
+              (z == 0 ? AZM3 : 0u) | (z == a.mz - 1 ? AZP3 : 0u);
+          const unsigned A2 = (x == 0 ? AXM3 : 0u) | (x == ex ? AXP3 : 0u) |
+                              (y == 0 ? AYM3 : 0u) | (y == ey ? AYP3 : 0u) |
+                              (z == 0 ? AZM3 : 0u) | (z == ez ? AZP3 : 0u);
+          const bool dirty =
+              old && (A2 != Af || ((m ^ pm) & ~Af & 0x3FFFu) != 0u);
+          if (old && !dirty) out = kKeep;  // keeps its level-(k+1) code
+          reclass += (unsigned)__popcll(__ballot(dirty));
+        }
+        const int q = (z - z0) * R + j;
+        stc[q * 64 + lane] = out;
+        if (WM) stm[q * 64 + lane] = (uint16_t)m;
+        const uint64_t bal = __ballot(live && code_is_critical(code));
+        wbits = lane == q ? bal : wbits;
+      }
+    };
+
+    // Prologue: planes z0-1, z0 derived; z0+1 .. z0+3 in flight.
+    Plane<R> W[3];
+    PlaneLoad<R> pf[3];
+    {
+      PlaneLoad<R> d0, d1;
+      load(z0 - 1, d0);
+      load(z0, d1);
+#pragma unroll
+      for (int s = 0; s < 3; s++) load(z0 + 1 + s, pf[s]);
+      derive(d0, W[0]);
+      derive(d1, W[1]);
     }
-    if (need) {
-      const unsigned code = A == 0u ? (unsigned)slut[m] : boundary_code3(slut, m, A);
-      crit = code_is_critical(code);
-      a.codes[(int64_t)z * a.sz + col_off] = (uint8_t)code;
-    }
-    const uint64_t bal = __ballot(crit);
-    if (lane == 0 && y < a.my) bits_row[(int64_t)z * bits_plane] = bal;
-    if (PROG) {
-      const uint64_t d = __ballot(old_dirty);
-      if (lane == 0 && d) atomicAdd(&s_reclass, (unsigned)__popcll(d));
+    for (int zb = z0; zb < z1; zb += U) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int z = zb + u;
+        derive(pf[u % 3], W[(u + 2) % 3]);  // plane z+1
+        load(z + 4, pf[u % 3]);
+        step(z, W[u % 3], W[(u + 1) % 3], W[(u + 2) % 3]);
+      }
     }
 
-    // ring advance: plane z+H+1 into the slot of plane z-H, next loads
-    store_plane(slot_of(z + H + 1), pfA);
-#pragma unroll
-    for (int k = 0; k < RPW; k++) {
-      pfA[k][0] = pfB[k][0];
-      pfA[k][1] = pfB[k][1];
+    // Write the staged tile.  Rows of a full-width tile at stride 1 leave
+    // as dwords (16 lanes per 64-byte row); rows that may hold a kept code,
+    // partial tiles and strided levels byte by byte.
+    const int nz = z1 - z0;
+    const int nrows = nz * R;
+    const bool wide = a.sx == 1 && x0 + 64 <= a.mx && (a.sy & 3) == 0 &&
+                      ((uintptr_t)a.codes & 3) == 0;
+    auto row_needs_bytes = [&](int q) {
+      const int z = z0 + q / R, j = q % R;
+      return !wide || (RP && !(z & 1) && !(j & 1));
+    };
+    for (int qb = 0; qb < nrows; qb += 4) {
+      const int q = qb + (lane >> 4), part = lane & 15;
+      const int y = y0 + q % R, z = z0 + q / R;
+      if (q < nrows && y < a.my && !row_needs_bytes(q)) {
+        const uint32_t v4 = *reinterpret_cast<const uint32_t *>(stc + q * 64 + part * 4);
+        *reinterpret_cast<uint32_t *>(a.codes + (int64_t)z * a.sz +
+                                      (int64_t)y * a.sy + x0 + part * 4) = v4;
+      }
     }
-    load_plane(z + H + 3, pfB);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 7; i++) {
-      P0[i] = P1[i];
-      P1[i] = P2[i];
+    for (int q = 0; q < nrows; q++) {
+      const int y = y0 + q % R, z = z0 + q / R;
+      if (y < a.my && row_needs_bytes(q)) {
+        const uint8_t b = stc[q * 64 + lane];
+        if (b != kKeep)
+          a.codes[(int64_t)z * a.sz + (int64_t)y * a.sy + (int64_t)x * a.sx] = b;
+      }
+    }
+    {
+      const int y = y0 + lane % R, z = z0 + lane / R;
+      if (lane < nrows && y < a.my)
+        a.bits[((int64_t)z * a.my + y) * a.rowwords + tx] = wbits;
+    }
+    if (WM) {
+      for (int q = 0; q < nrows; q++) {
+        const int y = y0 + q % R, z = z0 + q / R;
+        if (y < a.my && col)
+          omasks[((int64_t)z * a.my + y) * a.mx + x] = stm[q * 64 + lane];
+      }
     }
   }
-  if (PROG) {
-    __syncthreads();
-    if (tid == 0 && s_reclass) atomicAdd(a.reclass, s_reclass);
-  }
+  if (__ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
+  if (RP && lane == 0 && reclass) atomicAdd(&s_reclass, reclass);
+  __syncthreads();
+  if (RP && tid == 0) a.reclass_part[blockIdx.x] = s_reclass;
 }
 
 // ---------------------------------------------------------------------------
-// 2D classification: one block = 256 consecutive x of a level row, marching
-// along y over `zchunk` rows; 3-row register window of (x-1, x, x+1).
+// 2D classification: a wave tile is 64 x by kYChunk2 rows, marched along y.
 // ---------------------------------------------------------------------------
-template <int H, bool PROG>
-__global__ __launch_bounds__(kTile2X) void classify2d_kernel(ClassifyArgs a) {
-  constexpr int NT = kTile2X;
-  constexpr int TXH = kTile2X + 2 * H;
-  constexpr int NS = 2 * H + 2;  // LDS ring of rows, sized as in classify3d
-  __shared__ float sr[NS * TXH];
+struct Row2 {
+  float v, l, r;
+  unsigned pm;
+};
+struct RowLoad2 {
+  float v, h;
+  unsigned pm;
+};
+
+template <bool RP, bool WM>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
+    ClassifyArgs a) {
+  constexpr int NW = kWavesPerBlock;
+  constexpr int YC = kYChunk2;
+  constexpr int U = kUnroll;
+  constexpr int PF = 6;  // rows in flight
+  static_assert(YC % U == 0 && YC <= 64, "tile depth");
   __shared__ uint8_t slut[kLut2Size];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][YC * 64];
+  __shared__ uint8_t smask[WM ? NW : 1][WM ? YC * 64 : 4];
   __shared__ unsigned s_reclass;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int id = xcd_block_id();
-  const int tx = id % a.ntx, yc = id / a.ntx;
-  const int x0 = tx * kTile2X, y0 = yc * a.zchunk;
-  const int y1 = min(y0 + a.zchunk, a.my);
-
-  for (int i = id * NT + tid; i < a.lb_n; i += (int)gridDim.x * NT)
-    a.lb_state[i] = 0ull;
-  if (id == 0 && tid == 0) *a.lb_counter = 0u;
-  if (PROG && tid == 0) s_reclass = 0u;
   if (tid < kLut2Size) slut[tid] = a.lut[tid];
-
-  auto load_row = [&](int y, float (&v)[2]) {
-    v[0] = 0.f;
-    v[1] = 0.f;
-    if (y >= 0 && y < a.my) {
-      const float *row = a.f + (int64_t)y * a.sy;
-      const int x = x0 + tid;
-      if (x < a.mx) v[0] = row[(int64_t)x * a.sx];
-      if (tid < 2 * H) {
-        const int c = tid < H ? tid : kTile2X + tid;
-        const int xh = x0 - H + c;
-        if (xh >= 0 && xh < a.mx) v[1] = row[(int64_t)xh * a.sx];
-      }
-    }
-  };
-  auto store_row = [&](int slot, const float (&v)[2]) {
-    float *r = sr + slot * TXH;
-    r[H + tid] = v[0];
-    if (tid < 2 * H) r[tid < H ? tid : kTile2X + tid] = v[1];
-  };
-  auto triple = [&](int slot, float (&R)[3]) {
-    const float *q = sr + slot * TXH + H + tid;
-    R[0] = q[-1];
-    R[1] = q[0];
-    R[2] = q[1];
-  };
-  auto slot_of = [&](int y) { return (y - y0 + H) % NS; };
-
-  {
-    float pro[2 * H + 1][2];
-#pragma unroll
-    for (int i = 0; i < 2 * H + 1; i++) load_row(y0 - H + i, pro[i]);
-#pragma unroll
-    for (int i = 0; i < 2 * H + 1; i++) store_row(i, pro[i]);
-  }
-  constexpr int PF = 4;  // rows in flight
-  float pf[PF][2];
-#pragma unroll
-  for (int i = 0; i < PF; i++) load_row(y0 + H + 1 + i, pf[i]);
+  if (tid == 0) s_reclass = 0u;
   __syncthreads();
-  float R0[3], R1[3], R2[3];
-  triple(slot_of(y0 - 1), R0);
-  triple(slot_of(y0), R1);
 
-  const int x = x0 + tid;
-  const int xw0 = x0 + 64 * w;
-  const bool col_active = x < a.mx;
-  const bool wave_x_inner = xw0 > 0 && xw0 + 64 < a.mx;
+  bool nan_seen = false;
+  unsigned reclass = 0;
+  const int nwaves = (int)gridDim.x * NW;
+  const uint8_t *pmasks = reinterpret_cast<const uint8_t *>(a.prev_masks);
+  uint8_t *omasks = reinterpret_cast<uint8_t *>(a.masks);
 
-  for (int y = y0; y < y1; y++) {
-    triple(slot_of(y + 1), R2);
-    const float c = R1[1];
-    const float nb[6] = {R1[0], R1[2], R0[1], R2[1], R0[0], R2[2]};
-    const unsigned m = mask2(c, nb);
-    if (col_active && c != c) *a.nan_flag = a.gen;
-    unsigned A = 0;
-    if (!(wave_x_inner && y > 0 && y < a.my - 1)) {
-      A = (x == 0 ? AXM2 : 0u) | (x == a.mx - 1 ? AXP2 : 0u) |
-          (y == 0 ? AYM2 : 0u) | (y == a.my - 1 ? AYP2 : 0u);
-    }
-    bool need = col_active, old_dirty = false, crit = false;
-    if (PROG) {
-      const bool old = col_active && !((x | y) & 1);
-      if (old) {
-        const float *qm = sr + slot_of(y - 2) * TXH + H + tid;
-        const float *q0 = sr + slot_of(y) * TXH + H + tid;
-        const float *qp = sr + slot_of(y + 2) * TXH + H + tid;
-        const float fn[6] = {q0[-2], q0[2], qm[0], qp[0], qm[-2], qp[2]};
-        const unsigned m2 = mask2(c, fn);
+  for (int t = xcd_block_id() * NW + w; t < a.ntiles; t += nwaves) {
+    const int tx = t % a.ntx, yc = t / a.ntx;
+    const int x0 = tx * 64, y0 = yc * YC;
+    const int y1 = min(y0 + YC, a.my);
+    const int x = x0 + lane;
+    const bool col = x < a.mx;
+    const int xc = min(x, a.mx - 1);
+    const int xh = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + 64, a.mx - 1) : xc);
+    const int64_t xoff = (int64_t)xc * a.sx, hoff = (int64_t)xh * a.sx;
+    const int pxc = min(xc >> 1, a.pmx - 1);
+
+    auto load = [&](int y, RowLoad2 &d) {
+      const int ycl = min(max(y, 0), a.my - 1);
+      const float *row = a.f + (int64_t)ycl * a.sy;
+      d.v = row[xoff];
+      d.h = row[hoff];
+      if (RP) d.pm = pmasks[(int64_t)min(ycl >> 1, a.pmy - 1) * a.pmx + pxc];
+    };
+    auto derive = [&](const RowLoad2 &d, Row2 &p) {
+      p.v = d.v;
+      p.l = from_left(d.h, d.v);
+      p.r = from_right(d.h, d.v);
+      if (RP) p.pm = d.pm;
+    };
+    uint64_t wbits = 0;
+    uint8_t *stc = scode[w];
+    uint8_t *stm = smask[WM ? w : 0];
+
+    auto step = [&](int y, const Row2 &lo, const Row2 &mid, const Row2 &hi) {
+      const bool live = y < y1 && col;
+      const float c = mid.v;
+      unsigned m = 0;
+      m = push_sign(m, hi.r - c);   // 5 (1,1)
+      m = push_sign(m, c - lo.l);   // 4 (-1,-1)
+      m = push_sign(m, hi.v - c);   // 3 (0,1)
+      m = push_sign(m, c - lo.v);   // 2 (0,-1)
+      m = push_sign(m, mid.r - c);  // 1 (1,0)
+      m = push_sign(m, c - mid.l);  // 0 (-1,0)
+      m ^= kPos2;
+      if (special_centre(c)) {
+        const float nb[6] = {mid.l, mid.r, lo.v, hi.v, lo.l, hi.r};
+        m = mask2(c, nb);
+        nan_seen |= live && (c != c);
+      }
+      const bool inner = y > 0 && y < a.my - 1 && x0 > 0 && x0 + 64 < a.mx;
+      unsigned A = 0;
+      if (!inner)
+        A = (x == 0 ? AXM2 : 0u) | (x == a.mx - 1 ? AXP2 : 0u) |
+            (y == 0 ? AYM2 : 0u) | (y == a.my - 1 ? AYP2 : 0u);
+      const unsigned code = A == 0u ? (unsigned)slut[m] : boundary_code2(slut, m, A);
+      uint8_t out = live ? (uint8_t)code : kKeep;
+      if (RP && !(y & 1)) {
+        const bool old = live && !(x & 1);
         const int ex = 2 * ((a.mx - 1) >> 1), ey = 2 * ((a.my - 1) >> 1);
-        const unsigned Afull = (x == 0 ? AXM2 : 0u) |
-                               (x == a.mx - 1 ? AXP2 : 0u) |
-                               (y == 0 ? AYM2 : 0u) |
-                               (y == a.my - 1 ? AYP2 : 0u);
+        const unsigned Af = (x == 0 ? AXM2 : 0u) | (x == a.mx - 1 ? AXP2 : 0u) |
+                            (y == 0 ? AYM2 : 0u) | (y == a.my - 1 ? AYP2 : 0u);
         const unsigned A2 = (x == 0 ? AXM2 : 0u) | (x == ex ? AXP2 : 0u) |
                             (y == 0 ? AYM2 : 0u) | (y == ey ? AYP2 : 0u);
-        old_dirty = (A2 != Afull) || (((m ^ m2) & ~Afull & 0x3Fu) != 0u);
-        if (!old_dirty) {
-          need = false;
-          const int xp = x >> 1, yp = y >> 1;
-          const uint64_t wb =
-              a.prev_bits[(int64_t)yp * a.prev_rowwords + (xp >> 6)];
-          crit = (wb >> (xp & 63)) & 1ull;
-        }
+        const bool dirty = old && (A2 != Af || ((m ^ mid.pm) & ~Af & 0x3Fu) != 0u);
+        if (old && !dirty) out = kKeep;
+        reclass += (unsigned)__popcll(__ballot(dirty));
+      }
+      const int q = y - y0;
+      stc[q * 64 + lane] = out;
+      if (WM) stm[q * 64 + lane] = (uint8_t)m;
+      const uint64_t bal = __ballot(live && code_is_critical(code));
+      wbits = lane == q ? bal : wbits;
+    };
+
+    Row2 W[3];
+    RowLoad2 pf[PF];
+    {
+      RowLoad2 d0, d1;
+      load(y0 - 1, d0);
+      load(y0, d1);
+#pragma unroll
+      for (int s = 0; s < PF; s++) load(y0 + 1 + s, pf[s]);
+      derive(d0, W[0]);
+      derive(d1, W[1]);
+    }
+    for (int yb = y0; yb < y1; yb += U) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int y = yb + u;
+        derive(pf[u % PF], W[(u + 2) % 3]);
+        load(y + 1 + PF, pf[u % PF]);
+        step(y, W[u % 3], W[(u + 1) % 3], W[(u + 2) % 3]);
       }
     }
-    if (need) {
-      const unsigned code = A == 0u ? (unsigned)slut[m] : boundary_code2(slut, m, A);
-      crit = code_is_critical(code);
-      a.codes[(int64_t)y * a.sy + (int64_t)x * a.sx] = (uint8_t)code;
-    }
-    const uint64_t bal = __ballot(crit);
-    if (lane == 0 && xw0 < a.mx)
-      a.bits[(int64_t)y * a.rowwords + (xw0 >> 6)] = bal;
-    if (PROG) {
-      const uint64_t d = __ballot(old_dirty);
-      if (lane == 0 && d) atomicAdd(&s_reclass, (unsigned)__popcll(d));
-    }
 
-    store_row(slot_of(y + H + 1), pf[0]);
-#pragma unroll
-    for (int i = 0; i + 1 < PF; i++) {
-      pf[i][0] = pf[i + 1][0];
-      pf[i][1] = pf[i + 1][1];
+    const int nrows = y1 - y0;
+    const bool wide = a.sx == 1 && x0 + 64 <= a.mx && (a.sy & 3) == 0 &&
+                      ((uintptr_t)a.codes & 3) == 0;
+    for (int qb = 0; qb < nrows; qb += 4) {
+      const int q = qb + (lane >> 4), part = lane & 15;
+      const int y = y0 + q;
+      if (q < nrows && wide && !(RP && !(y & 1))) {
+        const uint32_t v4 = *reinterpret_cast<const uint32_t *>(stc + q * 64 + part * 4);
+        *reinterpret_cast<uint32_t *>(a.codes + (int64_t)y * a.sy + x0 + part * 4) = v4;
+      }
     }
-    load_row(y + H + 1 + PF, pf[PF - 1]);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-      R0[i] = R1[i];
-      R1[i] = R2[i];
+    for (int q = 0; q < nrows; q++) {
+      const int y = y0 + q;
+      if (!wide || (RP && !(y & 1))) {
+        const uint8_t b = stc[q * 64 + lane];
+        if (b != kKeep) a.codes[(int64_t)y * a.sy + (int64_t)x * a.sx] = b;
+      }
+    }
+    if (lane < nrows) a.bits[(int64_t)(y0 + lane) * a.rowwords + tx] = wbits;
+    if (WM) {
+      for (int q = 0; q < nrows; q++)
+        if (col) omasks[(int64_t)(y0 + q) * a.mx + x] = stm[q * 64 + lane];
     }
   }
-  if (PROG) {
-    __syncthreads();
-    if (tid == 0 && s_reclass) atomicAdd(a.reclass, s_reclass);
-  }
+  if (__ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
+  if (RP && lane == 0 && reclass) atomicAdd(&s_reclass, reclass);
+  __syncthreads();
+  if (RP && tid == 0) a.reclass_part[blockIdx.x] = s_reclass;
 }
 
 // ---------------------------------------------------------------------------
-// Compaction: bitmask -> ascending index list.
+// Compaction: bitmask -> ascending index list, in two passes without atomics
+// or waiting: count_kernel stores the number of set bits of every chunk of
+// kChunkWords words; expand_kernel sums the counts of the chunks before its
+// own, then writes the indices of its chunk.
 // ---------------------------------------------------------------------------
-constexpr uint64_t kFlagAggregate = 1ull << 62;
-constexpr uint64_t kFlagPrefix = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1ull;
-constexpr long kSpinLimit = 1L << 26;
-
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, l);
   const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), l);
   return ((uint64_t)hi << 32) | lo;
 }
 
-__global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactArgs a) {
-  __shared__ int s_chunk;
-  __shared__ int64_t s_wtot[kCompactThreads / 64];
-  __shared__ int64_t s_prefix;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) s_chunk = (int)atomicAdd(a.lb_counter, 1u);
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *scratch) {
+  // scratch: kCompactThreads / 64 entries
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) scratch[w] = v;
   __syncthreads();
-  const int chunk = s_chunk;  // ids follow the order in which blocks start
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kCompactThreads / 64; i++) s += scratch[i];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kCompactThreads) void count_kernel(CompactArgs a) {
+  __shared__ int s_red[kCompactThreads / 64];
+  __shared__ unsigned s_ured[kCompactThreads / 64];
+  const int chunk = blockIdx.x, tid = threadIdx.x;
+  const int64_t wthr = (int64_t)chunk * kChunkWords + (int64_t)tid * kCompactWordsPerThread;
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kCompactWordsPerThread; k++)
+    if (wthr + k < a.words) cnt += __popcll(a.bits[wthr + k]);
+  const int tot = block_sum(cnt, s_red);
+  if (tid == 0) a.counts[chunk] = tot;
+  if (chunk == 0 && a.reclass_out) {
+    unsigned r = 0;
+    for (int i = tid; i < a.reclass_n; i += kCompactThreads) r += a.reclass_part[i];
+    r = block_sum(r, s_ured);
+    if (tid == 0) *a.reclass_out = r;
+  }
+}
+
+__global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) {
+  __shared__ int64_t s_red[kCompactThreads / 64];
+  __shared__ int s_wtot[kCompactThreads / 64];
+  const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int64_t part = 0;
+  for (int i = tid; i < chunk; i += kCompactThreads) part += a.counts[i];
+  const int64_t prefix = block_sum(part, s_red);
+
   const int64_t wfirst = (int64_t)chunk * kChunkWords;
   const int64_t wthr = wfirst + (int64_t)tid * kCompactWordsPerThread;
-
   uint64_t wd[kCompactWordsPerThread];
   int cnt = 0;
 #pragma unroll
@@ -488,59 +619,17 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactArgs a)
     if (i < w) woff += s_wtot[i];
     btot += s_wtot[i];
   }
-
-  if (tid == 0) {
-    uint64_t *st = a.lb_state;
-    int64_t prefix = 0;
-    if (chunk == 0) {
-      __hip_atomic_store(&st[0], kFlagPrefix | (uint64_t)btot, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&st[chunk], kFlagAggregate | (uint64_t)btot,
-                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      long spins = 0;
-      int i = chunk - 1;
-      while (i >= 0) {
-        const uint64_t v = __hip_atomic_load(&st[i], __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t flag = v >> 62;
-        if (flag == 0) {
-          // Chunk i belongs to a block that started earlier and waits only
-          // on chunks before it, so it publishes in finite time; the limit
-          // only guards against a broken invariant.
-          if (++spins > kSpinLimit) {
-            *a.err_flag = a.gen;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        prefix += (int64_t)(v & kValueMask);
-        if (flag == 2) break;
-        --i;
-      }
-      __hip_atomic_store(&st[chunk], kFlagPrefix | (uint64_t)(prefix + btot),
-                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_prefix = prefix;
-  }
-  __syncthreads();
   const int64_t base = a.level_base[a.slot];
-  const int64_t my_off = base + s_prefix + woff + (incl - cnt);
+  const int64_t my_off = base + prefix + woff + (incl - cnt);
 
   if (chunk == a.nchunks - 1 && tid == 0) {
-    const int64_t total = s_prefix + btot;
+    const int64_t total = prefix + btot;
     a.level_base[a.slot + 1] = base + total;
-    if (a.count_dev) {
-      int64_t out = total;
-      if (*a.nan_flag == a.gen) out = -1;
-      else if (*a.err_flag == a.gen) out = -2;
-      *a.count_dev = out;
-    }
+    if (a.count_dev) *a.count_dev = (*a.nan_flag == a.gen) ? -1 : total;
   }
-  if (chunk == 0 && tid == 0 && a.zero_next) *a.zero_next = 0u;
 
-  // Wave-cooperative expansion of the wave's 256 words, in index order.
+  // Wave-cooperative expansion of the wave's 256 words, in index order:
+  // every store instruction writes consecutive list entries.
   const int64_t gw0 = wfirst + (int64_t)w * 64 * kCompactWordsPerThread;
   if (gw0 >= a.words) return;
   int64_t r = gw0 / a.rowwords;
@@ -580,51 +669,79 @@ __global__ __launch_bounds__(kCompactThreads) void compact_kernel(CompactArgs a)
   }
 }
 
+// Persistent grid size: resident blocks per CU x CUs, at most 8 per CU.
+template <typename K>
+int persistent_blocks(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) !=
+          hipSuccess)
+    return 256;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+  return cus * per_cu;
+}
+
+template <typename K>
+hipError_t launch_persistent(K kernel, const ClassifyArgs &a, hipStream_t st,
+                             int *grid_out) {
+  const int threads = 64 * kWavesPerBlock;
+  static const int nb = persistent_blocks(kernel, threads);
+  const int want = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int g = want < nb ? want : nb;
+  *grid_out = g;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)g), dim3(threads), 0, st, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-int classify3d_zchunk(int mx, int my, int mz) {
-  const int64_t cols = (int64_t)((mx + 63) / 64) * ((my + kTile3Y - 1) / kTile3Y);
-  // aim for >= 16 blocks per CU on 256 CUs, chunks of 16..64 planes
-  int zc = 64;
-  while (zc > 16 && cols * ((mz + zc - 1) / zc) < 4096) zc >>= 1;
-  return zc > mz ? mz : zc;
+int classify_max_blocks() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+          hipSuccess)
+    cus = 256;
+  return cus * 8;
 }
 
-int classify2d_ychunk(int mx, int my) {
-  const int64_t cols = (mx + kTile2X - 1) / kTile2X;
-  int yc = 256;
-  while (yc > 16 && cols * ((my + yc - 1) / yc) < 4096) yc >>= 1;
-  return yc > my ? my : yc;
+hipError_t launch_classify3d(ClassifyArgs a, bool read_prev, bool write_masks,
+                             hipStream_t st, int *grid_out) {
+  a.ntx = (a.mx + 63) / 64;
+  a.nty = (a.my + kTile3Y - 1) / kTile3Y;
+  a.nzc = (a.mz + kZChunk3 - 1) / kZChunk3;
+  a.ntiles = a.ntx * a.nty * a.nzc;
+  if (read_prev && write_masks)
+    return launch_persistent(classify3d_kernel<kTile3Y, true, true>, a, st, grid_out);
+  if (read_prev)
+    return launch_persistent(classify3d_kernel<kTile3Y, true, false>, a, st, grid_out);
+  if (write_masks)
+    return launch_persistent(classify3d_kernel<kTile3Y, false, true>, a, st, grid_out);
+  return launch_persistent(classify3d_kernel<kTile3Y, false, false>, a, st, grid_out);
 }
 
-hipError_t launch_classify3d(const ClassifyArgs &a, bool progressive,
-                             hipStream_t st) {
-  const int nzc = (a.mz + a.zchunk - 1) / a.zchunk;
-  const dim3 grid((unsigned)(a.ntx * a.nty * nzc));
-  if (progressive)
-    hipLaunchKernelGGL((classify3d_kernel<kTile3Y, 2, true>), grid,
-                       dim3(64 * kTile3Y), 0, st, a);
-  else
-    hipLaunchKernelGGL((classify3d_kernel<kTile3Y, 1, false>), grid,
-                       dim3(64 * kTile3Y), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_classify2d(const ClassifyArgs &a, bool progressive,
-                             hipStream_t st) {
-  const int nyc = (a.my + a.zchunk - 1) / a.zchunk;
-  const dim3 grid((unsigned)(a.ntx * nyc));
-  if (progressive)
-    hipLaunchKernelGGL((classify2d_kernel<2, true>), grid, dim3(kTile2X), 0,
-                       st, a);
-  else
-    hipLaunchKernelGGL((classify2d_kernel<1, false>), grid, dim3(kTile2X), 0,
-                       st, a);
-  return hipGetLastError();
+hipError_t launch_classify2d(ClassifyArgs a, bool read_prev, bool write_masks,
+                             hipStream_t st, int *grid_out) {
+  a.ntx = (a.mx + 63) / 64;
+  a.nty = 1;
+  a.nzc = (a.my + kYChunk2 - 1) / kYChunk2;
+  a.ntiles = a.ntx * a.nzc;
+  if (read_prev && write_masks)
+    return launch_persistent(classify2d_kernel<true, true>, a, st, grid_out);
+  if (read_prev)
+    return launch_persistent(classify2d_kernel<true, false>, a, st, grid_out);
+  if (write_masks)
+    return launch_persistent(classify2d_kernel<false, true>, a, st, grid_out);
+  return launch_persistent(classify2d_kernel<false, false>, a, st, grid_out);
 }
 
 hipError_t launch_compact(const CompactArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)a.nchunks),
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)a.nchunks),
+                     dim3(kCompactThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(expand_kernel, dim3((unsigned)a.nchunks),
                      dim3(kCompactThreads), 0, st, a);
   return hipGetLastError();
 }

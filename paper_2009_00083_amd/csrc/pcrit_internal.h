@@ -39,10 +39,19 @@ constexpr unsigned side_mask2(int axis, int side) {
 void build_link_table3(uint8_t *table);
 void build_link_table2(uint8_t *table);
 
-// Look-back chunk of the compaction kernel: 256 threads x 4 words of 64 bits.
+// Compaction chunk: 256 threads x 4 words of 64 bits (65536 vertices).
 constexpr int kCompactThreads = 256;
 constexpr int kCompactWordsPerThread = 4;
 constexpr int kChunkWords = kCompactThreads * kCompactWordsPerThread;
+
+// Tiles of the classification kernels.  Every wave owns a tile of 64
+// consecutive x (one sample per lane) by kTile3Y rows (3D) or one row (2D)
+// and marches it along the slowest axis; the waves of a block only share
+// the link-pattern table.
+constexpr int kWavesPerBlock = 4;
+constexpr int kTile3Y = 2;    // rows per 3D wave tile
+constexpr int kZChunk3 = 24;  // planes per 3D wave tile
+constexpr int kYChunk2 = 60;  // rows per 2D wave tile
 
 struct ClassifyArgs {
   const float *f;       // full-resolution field
@@ -53,19 +62,17 @@ struct ClassifyArgs {
   int64_t sx, sy, sz;   // element strides of one level step along x, y, z
   int mx, my, mz;       // level sizes (mz = 1 in 2D)
   int rowwords;         // ceil(mx / 64)
-  int zchunk;           // planes (3D) / rows (2D) per block
-  int ntx, nty;         // tiles along x and y (3D) / x (2D)
-  // progressive refinement (level k < k_max)
-  const uint64_t *prev_bits;  // critical bitmask of level k+1
-  int prev_rowwords, prev_my;
-  unsigned *reclass;          // counter of re-classified old vertices
-  // error reporting: flags hold the generation number of the failing call
-  unsigned *nan_flag;
+  int ntx, nty, nzc;    // wave tiles along x, y, z (2D: x, 1, y)
+  int ntiles;
+  // progressive refinement: polarity masks of the previous (coarser) level,
+  // dense in its level-local index order (uint16 in 3D, uint8 in 2D), and
+  // the masks of this level for the next one (same layout, may be null)
+  const void *prev_masks;
+  int pmx, pmy;         // sizes of the previous level along x and y
+  void *masks;
+  unsigned *reclass_part;  // progressive: one count per block
+  unsigned *nan_flag;      // set to gen if a level sample is NaN
   unsigned gen;
-  // reset of the look-back state used by the compaction that follows
-  uint64_t *lb_state;
-  int lb_n;
-  unsigned *lb_counter;
 };
 
 struct CompactArgs {
@@ -83,25 +90,24 @@ struct CompactArgs {
   int slot;
   int64_t *count_dev;   // may be null
   unsigned *nan_flag;
-  unsigned *err_flag;
   unsigned gen;
-  uint64_t *lb_state;
-  unsigned *lb_counter;
+  int *counts;          // per-chunk critical counts
   int nchunks;
-  unsigned *zero_next;  // counter to clear for the next level (may be null)
+  const unsigned *reclass_part;  // summed into *reclass_out (may be null)
+  int reclass_n;
+  unsigned *reclass_out;
 };
 
-hipError_t launch_classify3d(const ClassifyArgs &a, bool progressive,
-                             hipStream_t st);
-hipError_t launch_classify2d(const ClassifyArgs &a, bool progressive,
-                             hipStream_t st);
+// The classification launchers store the number of blocks they launched
+// (entries of reclass_part written) in *grid_out.
+hipError_t launch_classify3d(ClassifyArgs a, bool read_prev, bool write_masks,
+                             hipStream_t st, int *grid_out);
+hipError_t launch_classify2d(ClassifyArgs a, bool read_prev, bool write_masks,
+                             hipStream_t st, int *grid_out);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t st);
 
-// Launch geometry helpers (host).
-int classify3d_zchunk(int mx, int my, int mz);
-int classify2d_ychunk(int mx, int my);
-constexpr int kTile3X = 64;
-constexpr int kTile3Y = 4;
-constexpr int kTile2X = 256;
+// Number of persistent blocks a classification launch uses (the size of
+// the per-block reclass array).
+int classify_max_blocks();
 
 }  // namespace pcrit
