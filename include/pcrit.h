@@ -165,13 +165,15 @@ int pcrit_progressive(pcrit_ctx *ctx, void *hip_stream, const float *field,
                       float *level_ms_host, int64_t *reclassified_host,
                       pcrit_level_cb cb, void *user);
 
-/* Measurement.  With enable != 0 every later call records a HIP event pair
- * around each kernel it launches; pcrit_kernel_ms then returns, for the most
- * recent call, the durations in milliseconds of the classification kernel
- * and of the compaction kernel of each level (index = level, up to
- * max_levels entries each; -1 where no kernel ran).  The call synchronises
- * on the last recorded event. */
-int pcrit_set_kernel_timing(pcrit_ctx *ctx, int enable);
+/* Measurement.  Every later call records a HIP event pair on its stream
+ * around the classification kernel and around the compaction kernels of
+ * each level k whose bit k is set in level_mask (0 disables; the records
+ * add a few microseconds of stream time each).  pcrit_kernel_ms then
+ * returns, for the most recent call, the durations in milliseconds of the
+ * classification and of the compaction of each level (index = level, up to
+ * max_levels entries each; -1 where nothing was timed).  It synchronises on
+ * the last recorded event. */
+int pcrit_set_kernel_timing(pcrit_ctx *ctx, uint64_t level_mask);
 int pcrit_kernel_ms(pcrit_ctx *ctx, float *classify_ms_host,
                     float *compact_ms_host, int max_levels);
 

@@ -67,7 +67,7 @@ def _load():
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
                                       i64, vp, vp, vp, lib.LEVEL_CB, vp]
     lib.pcrit_progressive.restype = i32
-    lib.pcrit_set_kernel_timing.argtypes = [vp, i32]
+    lib.pcrit_set_kernel_timing.argtypes = [vp, ctypes.c_uint64]
     lib.pcrit_set_kernel_timing.restype = i32
     lib.pcrit_kernel_ms.argtypes = [vp, vp, vp, i32]
     lib.pcrit_kernel_ms.restype = i32
@@ -150,8 +150,18 @@ class Context:
         except Exception:
             pass
 
-    def set_kernel_timing(self, enable: bool):
-        _check(_load().pcrit_set_kernel_timing(self._ptr, int(bool(enable))),
+    def set_kernel_timing(self, levels=None):
+        """Time the kernels of the given levels (iterable of ints), all
+        levels (True), or none (None/False/empty)."""
+        if levels is True:
+            mask = (1 << 64) - 1
+        elif not levels:
+            mask = 0
+        else:
+            mask = 0
+            for k in levels:
+                mask |= 1 << int(k)
+        _check(_load().pcrit_set_kernel_timing(self._ptr, mask),
                "set_kernel_timing")
 
     def kernel_ms(self, max_levels: int = 40):

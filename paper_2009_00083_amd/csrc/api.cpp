@@ -78,14 +78,17 @@ struct pcrit_ctx {
   int64_t masks_bytes = 0;
   unsigned *reclass_part = nullptr;  // per-block counts of a progressive level
   int reclass_n = 0;
-  // flags[0] nan, [3 + i] re-classified old vertices of progressive step i
+  // One device status block read back with a single copy: level_base
+  // (kMaxLevels + 2 list offsets, [0] stays 0) followed by flags ([0] nan,
+  // [3 + i] re-classified old vertices of progressive step i).
+  void *status = nullptr;
+  int64_t *level_base = nullptr;
   unsigned *flags = nullptr;
-  int64_t *level_base = nullptr;  // kMaxLevels + 2 entries, [0] stays 0
-  // pinned host mirror for read-back
+  void *h_status = nullptr;  // pinned host mirror
   int64_t *h_base = nullptr;
   unsigned *h_flags = nullptr;
   unsigned gen = 0;
-  bool timing = false;
+  uint64_t timing = 0;  // bit k: time the kernels of level k
   hipEvent_t ev_start = nullptr;
   hipEvent_t ev_level[kMaxLevels + 1] = {};
   hipEvent_t kev[2][kMaxLevels][2] = {};
@@ -96,6 +99,17 @@ struct pcrit_ctx {
 namespace {
 
 constexpr int kFlagWords = 3 + kMaxLevels + 2;
+constexpr size_t kStatusBytes =
+    (kMaxLevels + 2) * sizeof(int64_t) + kFlagWords * sizeof(unsigned);
+
+// Copy the status block to the host and wait for the stream.
+int read_status(pcrit_ctx *c, hipStream_t s) {
+  if (hipMemcpyAsync(c->h_status, c->status, kStatusBytes,
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return PCRIT_E_HIP;
+  return PCRIT_OK;
+}
 
 int hip_status(hipError_t e) { return e == hipSuccess ? PCRIT_OK : PCRIT_E_HIP; }
 
@@ -144,7 +158,7 @@ unsigned next_gen(pcrit_ctx *c) {
 }
 
 void record_kernel(pcrit_ctx *c, int which, int level, int end, hipStream_t st) {
-  if (!c->timing || level < 0 || level >= kMaxLevels) return;
+  if (level < 0 || level >= kMaxLevels || !((c->timing >> level) & 1)) return;
   hipEvent_t &e = c->kev[which][level][end];
   if (!e) hipEventCreate(&e);
   hipEventRecord(e, st);
@@ -297,19 +311,19 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   build_link_table2(h2);
   bool ok = hipMalloc(&c->lut3, kLut3Size) == hipSuccess &&
             hipMalloc(&c->lut2, kLut2Size) == hipSuccess &&
-            hipMalloc(&c->flags, kFlagWords * sizeof(unsigned)) == hipSuccess &&
-            hipMalloc(&c->level_base, (kMaxLevels + 2) * sizeof(int64_t)) ==
-                hipSuccess &&
+            hipMalloc(&c->status, kStatusBytes) == hipSuccess &&
             hipMalloc(&c->reclass_part, classify_max_blocks() * sizeof(unsigned)) ==
                 hipSuccess &&
-            hipHostMalloc(&c->h_base, (kMaxLevels + 2) * sizeof(int64_t)) ==
-                hipSuccess &&
-            hipHostMalloc(&c->h_flags, kFlagWords * sizeof(unsigned)) ==
-                hipSuccess;
+            hipHostMalloc(&c->h_status, kStatusBytes) == hipSuccess;
+  if (ok) {
+    c->level_base = (int64_t *)c->status;
+    c->flags = (unsigned *)((char *)c->status + (kMaxLevels + 2) * sizeof(int64_t));
+    c->h_base = (int64_t *)c->h_status;
+    c->h_flags = (unsigned *)((char *)c->h_status + (kMaxLevels + 2) * sizeof(int64_t));
+  }
   ok = ok && hipMemcpy(c->lut3, h3, kLut3Size, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(c->lut2, h2, kLut2Size, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemset(c->flags, 0, kFlagWords * sizeof(unsigned)) == hipSuccess &&
-       hipMemset(c->level_base, 0, (kMaxLevels + 2) * sizeof(int64_t)) == hipSuccess;
+       hipMemset(c->status, 0, kStatusBytes) == hipSuccess;
   ok = ok && hipEventCreate(&c->ev_start) == hipSuccess;
   for (int i = 0; ok && i <= kMaxLevels; i++)
     ok = hipEventCreate(&c->ev_level[i]) == hipSuccess;
@@ -334,10 +348,8 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->masks[0]);
   hipFree(c->masks[1]);
   hipFree(c->reclass_part);
-  hipFree(c->flags);
-  hipFree(c->level_base);
-  if (c->h_base) hipHostFree(c->h_base);
-  if (c->h_flags) hipHostFree(c->h_flags);
+  hipFree(c->status);
+  if (c->h_status) hipHostFree(c->h_status);
   if (c->ev_start) hipEventDestroy(c->ev_start);
   for (int i = 0; i <= kMaxLevels; i++)
     if (c->ev_level[i]) hipEventDestroy(c->ev_level[i]);
@@ -373,12 +385,7 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
                      nullptr);
   if (st) return st;
   if (!crit_count_host) return PCRIT_OK;
-  if (hipMemcpyAsync(c->h_base, c->level_base, 2 * sizeof(int64_t),
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(c->h_flags, c->flags, 2 * sizeof(unsigned),
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return PCRIT_E_HIP;
+  if (read_status(c, s)) return PCRIT_E_HIP;
   const int64_t count = c->h_base[1] - c->h_base[0];
   *crit_count_host = count;
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
@@ -427,19 +434,11 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
     if (st) return st;
     if (hipEventRecord(c->ev_level[i], s) != hipSuccess) return PCRIT_E_HIP;
     if (cb) {
-      if (hipMemcpyAsync(c->h_base, c->level_base, (i + 2) * sizeof(int64_t),
-                         hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess)
-        return PCRIT_E_HIP;
+      if (read_status(c, s)) return PCRIT_E_HIP;
       cb(k, c->h_base[i + 1] - c->h_base[i], user);
     }
   }
-  if (hipMemcpyAsync(c->h_base, c->level_base, (kmax + 2) * sizeof(int64_t),
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(c->h_flags, c->flags, kFlagWords * sizeof(unsigned),
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return PCRIT_E_HIP;
+  if (read_status(c, s)) return PCRIT_E_HIP;
   if (level_offsets_host)
     for (int i = 0; i <= kmax + 1; i++) level_offsets_host[i] = c->h_base[i];
   if (reclassified_host)
@@ -456,9 +455,9 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   return c->h_base[kmax + 1] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
 
-int pcrit_set_kernel_timing(pcrit_ctx *c, int enable) {
+int pcrit_set_kernel_timing(pcrit_ctx *c, uint64_t level_mask) {
   if (!c) return PCRIT_E_ARG;
-  c->timing = enable != 0;
+  c->timing = level_mask;
   return PCRIT_OK;
 }
 

@@ -138,7 +138,7 @@ __device__ __forceinline__ unsigned push_sign(unsigned m, float d) {
 }
 // +-0, +-inf, NaN: the centres whose differences may not carry the order
 __device__ __forceinline__ bool special_centre(float c) {
-  return __builtin_amdgcn_class(c, 0x3 | 0x4 | 0x200 | 0x20 | 0x40);
+  return __builtin_amdgcn_classf(c, 0x3 | 0x4 | 0x200 | 0x20 | 0x40);
 }
 
 // One plane of a wave tile: rows y0-1 .. y0+R (index i = row - y0 + 1).
@@ -175,7 +175,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? ZC * R * 64 : 2];
   __shared__ unsigned s_reclass;
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // the wave index is the same in every lane: keep tile arithmetic scalar
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   {
     const uint4 *g = reinterpret_cast<const uint4 *>(a.lut);
     uint4 *s = reinterpret_cast<uint4 *>(slut);
@@ -193,8 +195,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   for (int t = xcd_block_id() * NW + w; t < a.ntiles; t += nwaves) {
     const int tx = t % a.ntx, rest = t / a.ntx;
     const int ty = rest % a.nty, zc = rest / a.nty;
-    const int x0 = tx * 64, y0 = ty * R, z0 = zc * ZC;
-    const int z1 = min(z0 + ZC, a.mz);
+    const int x0 = tx * 64, y0 = ty * R, z0 = zc * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.mz);
     const int x = x0 + lane;
     const bool col = x < a.mx;
 
@@ -411,7 +413,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
   __shared__ uint8_t smask[WM ? NW : 1][WM ? YC * 64 : 4];
   __shared__ unsigned s_reclass;
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < kLut2Size) slut[tid] = a.lut[tid];
   if (tid == 0) s_reclass = 0u;
   __syncthreads();
@@ -424,8 +427,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
 
   for (int t = xcd_block_id() * NW + w; t < a.ntiles; t += nwaves) {
     const int tx = t % a.ntx, yc = t / a.ntx;
-    const int x0 = tx * 64, y0 = yc * YC;
-    const int y1 = min(y0 + YC, a.my);
+    const int x0 = tx * 64, y0 = yc * a.zchunk;
+    const int y1 = min(y0 + a.zchunk, a.my);
     const int x = x0 + lane;
     const bool col = x < a.mx;
     const int xc = min(x, a.mx - 1);
@@ -571,7 +574,6 @@ __device__ __forceinline__ T block_sum(T v, T *scratch) {
 
 __global__ __launch_bounds__(kCompactThreads) void count_kernel(CompactArgs a) {
   __shared__ int s_red[kCompactThreads / 64];
-  __shared__ unsigned s_ured[kCompactThreads / 64];
   const int chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t wthr = (int64_t)chunk * kChunkWords + (int64_t)tid * kCompactWordsPerThread;
   int cnt = 0;
@@ -580,21 +582,24 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(CompactArgs a) {
     if (wthr + k < a.words) cnt += __popcll(a.bits[wthr + k]);
   const int tot = block_sum(cnt, s_red);
   if (tid == 0) a.counts[chunk] = tot;
+}
+
+// Also launched alone when the level fits one chunk (no counts needed).
+__global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) {
+  __shared__ int64_t s_red[kCompactThreads / 64];
+  __shared__ unsigned s_ured[kCompactThreads / 64];
+  __shared__ int s_wtot[kCompactThreads / 64];
+  const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int64_t part = 0;
+  for (int i = tid; i < chunk; i += kCompactThreads) part += a.counts[i];
+  const int64_t prefix = block_sum(part, s_red);
   if (chunk == 0 && a.reclass_out) {
     unsigned r = 0;
     for (int i = tid; i < a.reclass_n; i += kCompactThreads) r += a.reclass_part[i];
     r = block_sum(r, s_ured);
     if (tid == 0) *a.reclass_out = r;
   }
-}
-
-__global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) {
-  __shared__ int64_t s_red[kCompactThreads / 64];
-  __shared__ int s_wtot[kCompactThreads / 64];
-  const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int64_t part = 0;
-  for (int i = tid; i < chunk; i += kCompactThreads) part += a.counts[i];
-  const int64_t prefix = block_sum(part, s_red);
 
   const int64_t wfirst = (int64_t)chunk * kChunkWords;
   const int64_t wthr = wfirst + (int64_t)tid * kCompactWordsPerThread;
@@ -628,8 +633,9 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
     if (a.count_dev) *a.count_dev = (*a.nan_flag == a.gen) ? -1 : total;
   }
 
-  // Wave-cooperative expansion of the wave's 256 words, in index order:
-  // every store instruction writes consecutive list entries.
+  // Wave-cooperative expansion of the wave's 256 words, in index order: a
+  // word becomes the execution mask (its set lanes are the critical x), its
+  // lanes write consecutive list entries with one store.
   const int64_t gw0 = wfirst + (int64_t)w * 64 * kCompactWordsPerThread;
   if (gw0 >= a.words) return;
   int64_t r = gw0 / a.rowwords;
@@ -637,19 +643,20 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   int64_t yy = r % a.my, zz = r / a.my;
   const int64_t rowstep = a.s * a.nx;
   int64_t rowbase = rowstep * (yy + a.ny * zz);
-  for (int L = 0; L < 64; L++) {
+  const uint32_t lane_x = (uint32_t)(a.s * lane);
+  const int nw = (int)min((int64_t)64 * kCompactWordsPerThread, a.words - gw0);
+  for (int L = 0; L * kCompactWordsPerThread < nw; L++) {
     int64_t off = (int64_t)readlane64((uint64_t)my_off, L);
 #pragma unroll
     for (int k = 0; k < kCompactWordsPerThread; k++) {
       const uint64_t word = readlane64(wd[k], L);
       if (word) {
-        const unsigned rank = __builtin_amdgcn_mbcnt_hi(
-            (unsigned)(word >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)word, 0u));
-        if ((word >> lane) & 1ull) {
+        if (__builtin_amdgcn_inverse_ballot_w64(word)) {
+          const unsigned rank = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(word >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)word, 0u));
           const int64_t pos = off + rank;
           if (pos < a.cap) {
-            const uint32_t idx =
-                (uint32_t)(rowbase + a.s * (int64_t)(xw * 64 + lane));
+            const uint32_t idx = (uint32_t)(rowbase + a.s * (int64_t)xw * 64) + lane_x;
             a.crit[pos] = idx;
             if (a.crit_codes) a.crit_codes[pos] = a.codes[idx];
           }
@@ -665,7 +672,6 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
         rowbase = rowstep * (yy + a.ny * zz);
       }
     }
-    if (gw0 + (int64_t)(L + 1) * kCompactWordsPerThread >= a.words) break;
   }
 }
 
@@ -695,6 +701,16 @@ hipError_t launch_persistent(K kernel, const ClassifyArgs &a, hipStream_t st,
   return hipGetLastError();
 }
 
+// Tile depth along the marched axis: the deepest multiple of kUnroll (up to
+// `cap`) that still yields enough wave tiles to fill the GPU; small levels
+// get short tiles so that their march is short.
+int tile_depth(int64_t columns, int n, int cap) {
+  constexpr int64_t kWantTiles = 8192;
+  int d = cap;
+  while (d > kUnroll && columns * ((n + d - 1) / d) < kWantTiles) d -= kUnroll;
+  return d;
+}
+
 }  // namespace
 
 int classify_max_blocks() {
@@ -710,7 +726,8 @@ hipError_t launch_classify3d(ClassifyArgs a, bool read_prev, bool write_masks,
                              hipStream_t st, int *grid_out) {
   a.ntx = (a.mx + 63) / 64;
   a.nty = (a.my + kTile3Y - 1) / kTile3Y;
-  a.nzc = (a.mz + kZChunk3 - 1) / kZChunk3;
+  a.zchunk = tile_depth(a.ntx * a.nty, a.mz, kZChunk3);
+  a.nzc = (a.mz + a.zchunk - 1) / a.zchunk;
   a.ntiles = a.ntx * a.nty * a.nzc;
   if (read_prev && write_masks)
     return launch_persistent(classify3d_kernel<kTile3Y, true, true>, a, st, grid_out);
@@ -725,7 +742,8 @@ hipError_t launch_classify2d(ClassifyArgs a, bool read_prev, bool write_masks,
                              hipStream_t st, int *grid_out) {
   a.ntx = (a.mx + 63) / 64;
   a.nty = 1;
-  a.nzc = (a.my + kYChunk2 - 1) / kYChunk2;
+  a.zchunk = tile_depth(a.ntx, a.my, kYChunk2);
+  a.nzc = (a.my + a.zchunk - 1) / a.zchunk;
   a.ntiles = a.ntx * a.nzc;
   if (read_prev && write_masks)
     return launch_persistent(classify2d_kernel<true, true>, a, st, grid_out);
@@ -737,10 +755,12 @@ hipError_t launch_classify2d(ClassifyArgs a, bool read_prev, bool write_masks,
 }
 
 hipError_t launch_compact(const CompactArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)a.nchunks),
-                     dim3(kCompactThreads), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (a.nchunks > 1) {
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)a.nchunks),
+                       dim3(kCompactThreads), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(expand_kernel, dim3((unsigned)a.nchunks),
                      dim3(kCompactThreads), 0, st, a);
   return hipGetLastError();

@@ -62,6 +62,8 @@ struct ClassifyArgs {
   int64_t sx, sy, sz;   // element strides of one level step along x, y, z
   int mx, my, mz;       // level sizes (mz = 1 in 2D)
   int rowwords;         // ceil(mx / 64)
+  int zchunk;           // planes (3D) / rows (2D) per wave tile, a multiple
+                        // of 6, at most kZChunk3 / kYChunk2
   int ntx, nty, nzc;    // wave tiles along x, y, z (2D: x, 1, y)
   int ntiles;
   // progressive refinement: polarity masks of the previous (coarser) level,
