@@ -70,14 +70,15 @@ bool misaligned(const void *p, size_t a) {
 struct pcrit_ctx {
   int device = 0;
   uint8_t *lut3 = nullptr, *lut2 = nullptr;
-  uint64_t *bits[2] = {nullptr, nullptr};
+  uint64_t *bits = nullptr;  // critical bitmasks of the levels of one launch
   int64_t bits_words = 0;
   int *counts = nullptr;  // per-chunk critical counts of the compaction
   int64_t counts_n = 0;
+  uint8_t *lcodes = nullptr;  // dense codes of fused levels (for crit_codes)
+  int64_t lcodes_bytes = 0;
   void *masks[2] = {nullptr, nullptr};  // polarity masks, level ping-pong
   int64_t masks_bytes = 0;
-  unsigned *reclass_part = nullptr;  // per-block counts of a progressive level
-  int reclass_n = 0;
+  unsigned *reclass_part = nullptr;  // per block and level: re-classified
   // One device status block read back with a single copy: level_base
   // (kMaxLevels + 2 list offsets, [0] stays 0) followed by flags ([0] nan,
   // [3 + i] re-classified old vertices of progressive step i).
@@ -111,44 +112,15 @@ int read_status(pcrit_ctx *c, hipStream_t s) {
   return PCRIT_OK;
 }
 
-int hip_status(hipError_t e) { return e == hipSuccess ? PCRIT_OK : PCRIT_E_HIP; }
-
-int ensure_masks(pcrit_ctx *c, int64_t bytes) {
-  if (bytes <= c->masks_bytes) return PCRIT_OK;
+// Grow a scratch allocation (contents are not kept).
+int ensure(void **p, int64_t *have, int64_t bytes) {
+  if (bytes <= *have) return PCRIT_OK;
   hipDeviceSynchronize();
-  for (int i = 0; i < 2; i++) {
-    if (c->masks[i]) hipFree(c->masks[i]);
-    c->masks[i] = nullptr;
-  }
-  c->masks_bytes = 0;
-  for (int i = 0; i < 2; i++)
-    if (hipMalloc(&c->masks[i], (size_t)bytes) != hipSuccess) return PCRIT_E_OOM;
-  c->masks_bytes = bytes;
-  return PCRIT_OK;
-}
-
-int ensure_scratch(pcrit_ctx *c, int64_t words, int64_t chunks) {
-  if (words > c->bits_words) {
-    hipDeviceSynchronize();
-    for (int i = 0; i < 2; i++) {
-      if (c->bits[i]) hipFree(c->bits[i]);
-      c->bits[i] = nullptr;
-    }
-    c->bits_words = 0;
-    for (int i = 0; i < 2; i++)
-      if (hipMalloc(&c->bits[i], (size_t)words * 8) != hipSuccess)
-        return PCRIT_E_OOM;
-    c->bits_words = words;
-  }
-  if (chunks > c->counts_n) {
-    hipDeviceSynchronize();
-    if (c->counts) hipFree(c->counts);
-    c->counts = nullptr;
-    c->counts_n = 0;
-    if (hipMalloc(&c->counts, (size_t)chunks * sizeof(int)) != hipSuccess)
-      return PCRIT_E_OOM;
-    c->counts_n = chunks;
-  }
+  if (*p) hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  if (hipMalloc(p, (size_t)bytes) != hipSuccess) return PCRIT_E_OOM;
+  *have = bytes;
   return PCRIT_OK;
 }
 
@@ -166,76 +138,129 @@ void record_kernel(pcrit_ctx *c, int which, int level, int end, hipStream_t st) 
   if (end) c->last_kev = e;
 }
 
-// Enqueue classification (+ compaction) of one level.
-// Progressive steps: prev != null reads the polarity masks of the previous
-// (coarser) level from masks[mask_slot ^ 1]; write_masks stores this level's
-// masks into masks[mask_slot] for the next level.
-int enqueue_level(pcrit_ctx *c, hipStream_t st, const float *field,
-                  const Geom &g, const Geom *prev, bool write_masks,
-                  int bits_out, int mask_slot, uint8_t *codes, uint32_t *crit,
-                  uint8_t *crit_codes, int64_t cap, int slot,
-                  int64_t *count_dev, unsigned gen, unsigned *reclass) {
-  const bool progressive = prev != nullptr;
-  const int64_t chunks = (g.words + kChunkWords - 1) / kChunkWords;
+// One level of a launch.
+struct Step {
+  Geom g;
+  const Geom *prev = nullptr;  // previous (coarser) level, progressive only
+  bool dirty = false;          // test old vertices against `prev`
+  int mask_read = -1;          // masks slot holding prev's masks, or -1
+  int mask_write = -1;         // masks slot for this level's masks, or -1
+  int slot = 0;                // list slot (level_base index)
+  unsigned *reclass_out = nullptr;
+};
+
+int64_t level_vertices(const Geom &g) { return g.mx * g.my * g.mz; }
+
+// Scratch one launch of steps[0..n) needs.
+void launch_needs(const Step *steps, int n, bool with_codes, int64_t *words,
+                  int64_t *chunks, int64_t *lbytes) {
+  const bool fused = n > 1;
+  const int64_t cw = fused ? kFusedChunkWords : kChunkWords;
+  *words = *chunks = *lbytes = 0;
+  for (int l = 0; l < n; l++) {
+    *words += steps[l].g.words;
+    *chunks += (steps[l].g.words + cw - 1) / cw;
+    if (fused && l + 1 < n && with_codes) *lbytes += level_vertices(steps[l].g);
+  }
+}
+
+// Enqueue classification + compaction of steps[0..n): one level, or several
+// small levels fused into one launch of each kernel.  In a fused launch the
+// levels run concurrently: old vertices are tested against the previous
+// level's masks computed from the field, only the finest level stores its
+// codes at full resolution (its vertices include those of the others), and
+// the others keep dense level codes for crit_codes.
+int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
+                  const Step *steps, int n, uint8_t *codes, uint32_t *crit,
+                  uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
+                  unsigned gen) {
+  const bool fused = n > 1;
+  const int dim = steps[0].g.dim;
+  const int64_t cw = fused ? kFusedChunkWords : kChunkWords;
   ClassifyArgs a{};
   a.f = field;
   a.codes = codes;
-  a.bits = c->bits[bits_out];
-  a.lut = g.dim == 3 ? c->lut3 : c->lut2;
-  a.sx = g.s;
-  a.sy = g.s * g.nx;
-  a.sz = g.s * g.nx * g.ny;
-  a.mx = (int)g.mx;
-  a.my = (int)g.my;
-  a.mz = (int)g.mz;
-  a.rowwords = (int)g.rowwords;
-  if (progressive) {
-    a.prev_masks = c->masks[mask_slot ^ 1];
-    a.pmx = (int)prev->mx;
-    a.pmy = (int)prev->my;
-  }
-  if (write_masks) a.masks = c->masks[mask_slot];
+  a.lut = dim == 3 ? c->lut3 : c->lut2;
+  a.nl = n;
   a.reclass_part = c->reclass_part;
   a.nan_flag = &c->flags[0];
   a.gen = gen;
-  hipError_t e;
-  int grid = 0;
-  record_kernel(c, 0, g.level, 0, st);
-  if (g.dim == 3)
-    e = launch_classify3d(a, progressive, write_masks, st, &grid);
-  else
-    e = launch_classify2d(a, progressive, write_masks, st, &grid);
-  if (e != hipSuccess) return PCRIT_E_HIP;
-  record_kernel(c, 0, g.level, 1, st);
-
   CompactArgs b{};
-  b.bits = c->bits[bits_out];
-  b.words = g.words;
-  b.rowwords = (int)g.rowwords;
-  b.my = (int)g.my;
-  b.s = g.s;
-  b.nx = g.nx;
-  b.ny = g.ny;
+  b.nl = n;
+  int64_t woff = 0, loff = 0, chunks = 0;
+  int tiles = 0;
+  for (int l = 0; l < n; l++) {
+    const Step &sp = steps[l];
+    const Geom &g = sp.g;
+    const bool last = l == n - 1;
+    LevelDesc &d = a.lv[l];
+    d.sx = g.s;
+    d.sy = g.s * g.nx;
+    d.sz = g.s * g.nx * g.ny;
+    d.mx = (int)g.mx;
+    d.my = (int)g.my;
+    d.mz = (int)g.mz;
+    d.rowwords = (int)g.rowwords;
+    if (dim == 3)
+      plan_level3(d);
+    else
+      plan_level2(d);
+    d.tile_begin = tiles;
+    tiles += d.ntiles;
+    d.bits = c->bits + woff;
+    d.lcodes = fused && !last && crit_codes ? c->lcodes + loff : nullptr;
+    if (!fused && sp.mask_read >= 0) d.prev_masks = c->masks[sp.mask_read];
+    if (sp.prev) {
+      d.pmx = (int)sp.prev->mx;
+      d.pmy = (int)sp.prev->my;
+    }
+    if (sp.mask_write >= 0) d.masks = c->masks[sp.mask_write];
+    d.write_codes = !fused || last;
+    d.keep_clean = !fused && sp.dirty;
+    d.dirty = sp.dirty;
+
+    CompactLevel &q = b.lv[l];
+    q.bits = d.bits;
+    q.words = g.words;
+    q.rowwords = (int)g.rowwords;
+    q.mx = (int)g.mx;
+    q.my = (int)g.my;
+    q.s = g.s;
+    q.slot = sp.slot;
+    q.chunk_begin = (int)chunks;
+    q.lcodes = d.lcodes;
+    q.reclass_out = sp.reclass_out;
+    woff += g.words;
+    if (d.lcodes) loff += level_vertices(g);
+    chunks += (g.words + cw - 1) / cw;
+  }
+  a.ntiles = tiles;
+  const int tlevel = steps[n - 1].g.level;  // a launch is timed as its finest level
+  int grid = 0;
+  record_kernel(c, 0, tlevel, 0, st);
+  const Step &s0 = steps[0];
+  if (launch_classify(a, dim, !fused && s0.mask_read >= 0,
+                      !fused && s0.mask_write >= 0, st, &grid) != hipSuccess)
+    return PCRIT_E_HIP;
+  record_kernel(c, 0, tlevel, 1, st);
+
+  b.nchunks = (int)chunks;
+  b.nx = s0.g.nx;
+  b.ny = s0.g.ny;
   b.crit = crit;
   b.crit_codes = crit_codes;
   b.codes = codes;
   b.cap = cap;
   b.level_base = c->level_base;
-  b.slot = slot;
   b.count_dev = count_dev;
   b.nan_flag = &c->flags[0];
   b.gen = gen;
   b.counts = c->counts;
-  b.nchunks = (int)chunks;
-  if (progressive) {
-    b.reclass_part = c->reclass_part;
-    b.reclass_n = std::min(grid, c->reclass_n);
-    b.reclass_out = reclass;
-  }
-  record_kernel(c, 1, g.level, 0, st);
-  e = launch_compact(b, st);
-  if (e != hipSuccess) return PCRIT_E_HIP;
-  record_kernel(c, 1, g.level, 1, st);
+  b.reclass_part = c->reclass_part;
+  b.reclass_blocks = grid;
+  record_kernel(c, 1, tlevel, 0, st);
+  if (launch_compact(b, fused, st) != hipSuccess) return PCRIT_E_HIP;
+  record_kernel(c, 1, tlevel, 1, st);
   return PCRIT_OK;
 }
 
@@ -305,15 +330,14 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   if (hipSetDevice(hip_device) != hipSuccess) return PCRIT_E_HIP;
   pcrit_ctx *c = new pcrit_ctx();
   c->device = hip_device;
-  c->reclass_n = classify_max_blocks();
   uint8_t h3[kLut3Size], h2[kLut2Size];
   build_link_table3(h3);
   build_link_table2(h2);
   bool ok = hipMalloc(&c->lut3, kLut3Size) == hipSuccess &&
             hipMalloc(&c->lut2, kLut2Size) == hipSuccess &&
             hipMalloc(&c->status, kStatusBytes) == hipSuccess &&
-            hipMalloc(&c->reclass_part, classify_max_blocks() * sizeof(unsigned)) ==
-                hipSuccess &&
+            hipMalloc(&c->reclass_part, (size_t)classify_max_blocks() * kMaxFused *
+                                            sizeof(unsigned)) == hipSuccess &&
             hipHostMalloc(&c->h_status, kStatusBytes) == hipSuccess;
   if (ok) {
     c->level_base = (int64_t *)c->status;
@@ -342,9 +366,9 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipDeviceSynchronize();
   hipFree(c->lut3);
   hipFree(c->lut2);
-  hipFree(c->bits[0]);
-  hipFree(c->bits[1]);
+  hipFree(c->bits);
   hipFree(c->counts);
+  hipFree(c->lcodes);
   hipFree(c->masks[0]);
   hipFree(c->masks[1]);
   hipFree(c->reclass_part);
@@ -376,13 +400,17 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
   if (st) return st;
   if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
   hipStream_t s = (hipStream_t)hip_stream;
-  st = ensure_scratch(c, g.words, (g.words + kChunkWords - 1) / kChunkWords);
+  Step step;
+  step.g = g;
+  int64_t words, chunks, lbytes;
+  launch_needs(&step, 1, crit_codes != nullptr, &words, &chunks, &lbytes);
+  st = ensure((void **)&c->bits, &c->bits_words, words * 8);
+  if (!st) st = ensure((void **)&c->counts, &c->counts_n, chunks * (int64_t)sizeof(int));
   if (st) return st;
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
-  st = enqueue_level(c, s, field, g, nullptr, false, 0, 0, codes, crit,
-                     crit_codes, crit_capacity, 0, crit_count_dev, gen,
-                     nullptr);
+  st = enqueue_group(c, s, field, &step, 1, codes, crit, crit_codes,
+                     crit_capacity, crit_count_dev, gen);
   if (st) return st;
   if (!crit_count_host) return PCRIT_OK;
   if (read_status(c, s)) return PCRIT_E_HIP;
@@ -413,29 +441,76 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   }
   if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
   hipStream_t s = (hipStream_t)hip_stream;
-  int64_t max_words = 0;
-  for (int k = 0; k <= kmax; k++) max_words = std::max(max_words, geo[k].words);
-  st = ensure_scratch(c, max_words, (max_words + kChunkWords - 1) / kChunkWords);
-  if (st) return st;
-  if (kmax > 0) {
-    // masks of levels kmax .. 1 (the finest of them is the largest)
-    const Geom &g1 = geo[1];
-    st = ensure_masks(c, g1.mx * g1.my * g1.mz * (g1.dim == 3 ? 2 : 1));
-    if (st) return st;
+
+  // Steps in order (i = kmax - k) and their grouping into launches: the
+  // leading run of small levels is fused (up to kMaxFused per launch) unless
+  // a per-level callback wants each level to complete on its own.
+  Step steps[kMaxLevels];
+  for (int i = 0; i <= kmax; i++) {
+    const int k = kmax - i;
+    Step &sp = steps[i];
+    sp.g = geo[k];
+    sp.slot = i;
+    if (i > 0) {
+      sp.prev = &geo[k + 1];
+      sp.dirty = true;
+      sp.mask_read = (i - 1) & 1;
+      sp.reclass_out = &c->flags[3 + i];
+    }
   }
+  int group_end[kMaxLevels];  // launch of step i covers [i, group_end[i])
+  for (int i = 0; i <= kmax;) {
+    int j = i + 1;
+    if (!cb && level_vertices(steps[i].g) <= kSmallLevel)
+      while (j <= kmax && j - i < kMaxFused && level_vertices(steps[j].g) <= kSmallLevel)
+        j++;
+    group_end[i] = j;
+    // the last level of a launch stores its masks for the next launch
+    if (j <= kmax) steps[j - 1].mask_write = (j - 1) & 1;
+    i = j;
+  }
+  int64_t need_words = 0, need_chunks = 0, need_l = 0, need_masks = 0;
+  for (int i = 0; i <= kmax; i = group_end[i]) {
+    int64_t w, ch, lb;
+    launch_needs(&steps[i], group_end[i] - i, crit_codes != nullptr, &w, &ch, &lb);
+    need_words = std::max(need_words, w);
+    need_chunks = std::max(need_chunks, ch);
+    need_l = std::max(need_l, lb);
+    const Step &last = steps[group_end[i] - 1];
+    if (last.mask_write >= 0)
+      need_masks = std::max(need_masks,
+                            level_vertices(last.g) * (last.g.dim == 3 ? 2 : 1));
+  }
+  st = ensure((void **)&c->bits, &c->bits_words, need_words * 8);
+  if (!st) st = ensure((void **)&c->counts, &c->counts_n, need_chunks * (int64_t)sizeof(int));
+  if (!st) st = ensure((void **)&c->lcodes, &c->lcodes_bytes, need_l);
+  if (st) return st;
+  if (need_masks > c->masks_bytes) {
+    hipDeviceSynchronize();
+    for (int i = 0; i < 2; i++) {
+      if (c->masks[i]) hipFree(c->masks[i]);
+      c->masks[i] = nullptr;
+    }
+    c->masks_bytes = 0;
+    for (int i = 0; i < 2; i++)
+      if (hipMalloc(&c->masks[i], (size_t)need_masks) != hipSuccess) return PCRIT_E_OOM;
+    c->masks_bytes = need_masks;
+  }
+
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
   if (hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
-  for (int i = 0; i <= kmax; i++) {
-    const int k = kmax - i;
-    st = enqueue_level(c, s, field, geo[k], i > 0 ? &geo[k + 1] : nullptr,
-                       k > 0, i & 1, i & 1, codes, crit, crit_codes,
-                       crit_capacity, i, nullptr, gen, &c->flags[3 + i]);
+  for (int i = 0; i <= kmax; i = group_end[i]) {
+    const int n = group_end[i] - i;
+    st = enqueue_group(c, s, field, &steps[i], n, codes, crit, crit_codes,
+                       crit_capacity, nullptr, gen);
     if (st) return st;
-    if (hipEventRecord(c->ev_level[i], s) != hipSuccess) return PCRIT_E_HIP;
+    // levels of one launch complete together
+    for (int j = i; j < i + n; j++)
+      if (hipEventRecord(c->ev_level[j], s) != hipSuccess) return PCRIT_E_HIP;
     if (cb) {
       if (read_status(c, s)) return PCRIT_E_HIP;
-      cb(k, c->h_base[i + 1] - c->h_base[i], user);
+      cb(kmax - i, c->h_base[i + 1] - c->h_base[i], user);
     }
   }
   if (read_status(c, s)) return PCRIT_E_HIP;

@@ -53,63 +53,87 @@ constexpr int kTile3Y = 2;    // rows per 3D wave tile
 constexpr int kZChunk3 = 24;  // planes per 3D wave tile
 constexpr int kYChunk2 = 60;  // rows per 2D wave tile
 
+// Levels of at most kSmallLevel vertices are launch-latency bound; the
+// progressive driver classifies and compacts all of them in one launch each
+// (up to kMaxFused levels).
+constexpr int64_t kSmallLevel = 1 << 22;
+constexpr int kMaxFused = 16;
+
+// One level as the classification kernels see it.
+struct LevelDesc {
+  int64_t sx, sy, sz;     // element strides of one level step along x, y, z
+  int mx, my, mz;         // level sizes (mz = 1 in 2D)
+  int rowwords;           // ceil(mx / 64)
+  int zchunk;             // planes (3D) / rows (2D) per wave tile
+  int ntx, nty, ntiles;   // wave tiles along x and y (3D); x (2D); total
+  int tile_begin;         // first tile of this level in a fused launch
+  uint64_t *bits;         // critical bitmask, rowwords words per level row
+  uint8_t *lcodes;        // dense level-local codes (fused levels) or null
+  const void *prev_masks; // previous level's polarity masks (stored) or null
+  int pmx, pmy;           // previous level sizes along x and y
+  void *masks;            // this level's polarity masks for the next level
+  int write_codes;        // store codes into the full-resolution array
+  int keep_clean;         // clean old vertices keep their stored code
+  int dirty;              // test old vertices against the previous level
+                          // (its masks from prev_masks if set, else from
+                          // the field: the fused launches)
+};
+
 struct ClassifyArgs {
   const float *f;       // full-resolution field
   uint8_t *codes;       // full-resolution code bytes
-  uint64_t *bits;       // critical bitmask of this level, one padded row of
-                        // rowwords words per (y, z) level row
   const uint8_t *lut;   // link-pattern table (device)
-  int64_t sx, sy, sz;   // element strides of one level step along x, y, z
-  int mx, my, mz;       // level sizes (mz = 1 in 2D)
-  int rowwords;         // ceil(mx / 64)
-  int zchunk;           // planes (3D) / rows (2D) per wave tile, a multiple
-                        // of 6, at most kZChunk3 / kYChunk2
-  int ntx, nty, nzc;    // wave tiles along x, y, z (2D: x, 1, y)
-  int ntiles;
-  // progressive refinement: polarity masks of the previous (coarser) level,
-  // dense in its level-local index order (uint16 in 3D, uint8 in 2D), and
-  // the masks of this level for the next one (same layout, may be null)
-  const void *prev_masks;
-  int pmx, pmy;         // sizes of the previous level along x and y
-  void *masks;
-  unsigned *reclass_part;  // progressive: one count per block
+  int nl;               // levels in this launch (1, or several when fused)
+  int ntiles;           // wave tiles of all levels
+  LevelDesc lv[kMaxFused];
+  unsigned *reclass_part;  // per block and level: re-classified old vertices
   unsigned *nan_flag;      // set to gen if a level sample is NaN
   unsigned gen;
 };
 
-struct CompactArgs {
+// One level as the compaction kernels see it.
+struct CompactLevel {
   const uint64_t *bits;
   int64_t words;        // rows * rowwords
-  int rowwords;
-  int my;               // level rows per plane (rows of a 2D level)
+  int rowwords, mx, my;
   int64_t s;            // level stride
+  int slot;             // list of this level: level_base[slot] onwards
+  int chunk_begin;      // first chunk of this level (chunks in list order)
+  const uint8_t *lcodes;  // dense level codes for crit_codes, or null
+  unsigned *reclass_out;  // sum of reclass_part column `index`, or null
+};
+
+struct CompactArgs {
+  int nl;
+  int nchunks;          // chunks of all levels
+  CompactLevel lv[kMaxFused];
   int64_t nx, ny;       // full-resolution sizes
   uint32_t *crit;
   uint8_t *crit_codes;  // may be null
-  const uint8_t *codes;
+  const uint8_t *codes; // full-resolution codes (levels without lcodes)
   int64_t cap;
-  int64_t *level_base;  // reads level_base[slot], writes level_base[slot+1]
-  int slot;
-  int64_t *count_dev;   // may be null
+  int64_t *level_base;  // list offsets; [0] is 0
+  int64_t *count_dev;   // may be null: total of the last level
   unsigned *nan_flag;
   unsigned gen;
   int *counts;          // per-chunk critical counts
-  int nchunks;
-  const unsigned *reclass_part;  // summed into *reclass_out (may be null)
-  int reclass_n;
-  unsigned *reclass_out;
+  const unsigned *reclass_part;
+  int reclass_blocks;   // rows of reclass_part (blocks of the classify launch)
 };
 
-// The classification launchers store the number of blocks they launched
-// (entries of reclass_part written) in *grid_out.
-hipError_t launch_classify3d(ClassifyArgs a, bool read_prev, bool write_masks,
-                             hipStream_t st, int *grid_out);
-hipError_t launch_classify2d(ClassifyArgs a, bool read_prev, bool write_masks,
-                             hipStream_t st, int *grid_out);
-hipError_t launch_compact(const CompactArgs &a, hipStream_t st);
+// Fill the launch geometry of a level (tile depth, tile counts).
+void plan_level3(LevelDesc &l);
+void plan_level2(LevelDesc &l);
+// Chunks of kChunkWords words (single level) or kFusedChunkWords (fused).
+constexpr int kFusedWordsPerThread = 1;
+constexpr int kFusedChunkWords = kCompactThreads * kFusedWordsPerThread;
 
-// Number of persistent blocks a classification launch uses (the size of
-// the per-block reclass array).
+// Launchers; *grid_out receives the number of blocks of the classification.
+hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
+                           bool write_masks, hipStream_t st, int *grid_out);
+hipError_t launch_compact(const CompactArgs &a, bool fused, hipStream_t st);
+
+// Upper bound of the blocks of a classification launch.
 int classify_max_blocks();
 
 }  // namespace pcrit

@@ -236,6 +236,85 @@ def test_progressive_gauss64(ctx, dev):
     check_progressive(ctx, dev, fieldgen.config_field("gauss64"))
 
 
+def _dirty_old_vertices(f, k):
+    """Old vertices of level k (present at level k+1) whose neighbourhood
+    changed: a neighbour direction present at one of the two levels only, or
+    whose level-k neighbour v+d and level-(k+1) neighbour v+2d lie on
+    different sides of v in the order (value, then full-resolution index).
+    Counted directly on the level-k samples."""
+    s = 1 << k
+    offs = OFF3 if f.ndim == 3 else [(dx, dy, 0) for dx, dy in OFF2]
+    f3 = f if f.ndim == 3 else f[None]
+    lv = f3[::1 if f.ndim == 2 else s, ::s, ::s]
+    nzf, nyf, nxf = f3.shape
+    mz, my, mx = lv.shape
+    zz, yy, xx = np.meshgrid(np.arange(mz), np.arange(my), np.arange(mx), indexing="ij")
+    idx = (xx * s + nxf * (yy * s + nyf * (zz * (s if f.ndim == 3 else 1)))).astype(np.int64)
+    old = (xx % 2 == 0) & (yy % 2 == 0) & (zz % 2 == 0)
+    last = [2 * ((m - 1) // 2) for m in (mx, my, mz)]
+
+    def after(a, b, ia, ib):  # a comes after b
+        return (a > b) | ((a == b) & (ia > ib))
+
+    dirty = np.zeros(lv.shape, bool)
+    for dx, dy, dz in offs:
+        x1, y1, z1 = xx + dx, yy + dy, zz + dz
+        x2, y2, z2 = xx + 2 * dx, yy + 2 * dy, zz + 2 * dz
+        e1 = (x1 >= 0) & (x1 < mx) & (y1 >= 0) & (y1 < my) & (z1 >= 0) & (z1 < mz)
+        e2 = ((x2 >= 0) & (x2 <= last[0]) & (y2 >= 0) & (y2 <= last[1]) &
+              (z2 >= 0) & (z2 <= last[2]))
+        c1 = np.clip
+        a1 = lv[c1(z1, 0, mz - 1), c1(y1, 0, my - 1), c1(x1, 0, mx - 1)]
+        i1 = idx[c1(z1, 0, mz - 1), c1(y1, 0, my - 1), c1(x1, 0, mx - 1)]
+        a2 = lv[c1(z2, 0, mz - 1), c1(y2, 0, my - 1), c1(x2, 0, mx - 1)]
+        i2 = idx[c1(z2, 0, mz - 1), c1(y2, 0, my - 1), c1(x2, 0, mx - 1)]
+        flip = after(a1, lv, i1, idx) != after(a2, lv, i2, idx)
+        dirty |= (e1 != e2) | (e1 & e2 & flip)
+    return int((dirty & old).sum())
+
+
+@pytest.mark.parametrize("shape", [(37, 23, 19), (33, 33, 33), (17, 9, 40),
+                                   (301, 77), (129, 130)])
+@pytest.mark.parametrize("gen", ["tie", "gauss"])
+def test_progressive_unfused_and_reclassified(ctx, dev, shape, gen):
+    """A per-level callback makes every level a launch of its own (old
+    vertices tested against stored masks); without it the small levels share
+    one launch (masks recomputed from the field).  Both give the same lists,
+    codes and re-classification counts, and the counts match a direct count
+    of the old vertices whose neighbourhood changed."""
+    f = (fieldgen.tie_field(shape, 7, 3) if gen == "tie" else
+         fieldgen.gaussian_field(shape, 8, 6, noise=("uniform", 1e-3)))
+    ft = torch.from_numpy(f).to(dev)
+    seen = []
+    p1 = pc.progressive(ft, ctx=ctx, with_crit_codes=True,
+                        callback=lambda k, n, u: seen.append((k, n)))
+    torch.cuda.synchronize()
+    p2 = pc.progressive(ft, ctx=ctx, with_crit_codes=True)
+    torch.cuda.synchronize()
+    assert [k for k, _ in seen] == list(p1.levels)
+    assert [n for _, n in seen] == list(np.diff(p1.offsets))
+    assert np.array_equal(p1.offsets, p2.offsets)
+    n = int(p1.offsets[-1])  # entries past the last list are not written
+    assert torch.equal(p1.crit[:n], p2.crit[:n])
+    assert torch.equal(p1.crit_codes[:n], p2.crit_codes[:n])
+    assert torch.equal(p1.codes, p2.codes)
+    assert np.array_equal(p1.reclassified, p2.reclassified)
+    want = [0] + [_dirty_old_vertices(f, k) for k in p1.levels[1:]]
+    assert list(p1.reclassified) == want
+    check_progressive(ctx, dev, f)
+
+
+def test_progressive_special_values(ctx, dev):
+    f = fieldgen.tie_field((21, 22, 23), 9, 4)
+    vals = np.array([-np.inf, -0.0, 0.0, np.inf, 1.0], np.float32)
+    f = vals[f.astype(np.int64) % 5].astype(np.float32)
+    f.ravel()[::7] = -0.0
+    check_progressive(ctx, dev, f)
+    g = fieldgen.tie_field((45, 66), 9, 4)
+    g = vals[g.astype(np.int64) % 5].astype(np.float32)
+    check_progressive(ctx, dev, g)
+
+
 def test_determinism(ctx, dev):
     f = fieldgen.tie_field((40, 50, 70), 1, 2)
     a = gpu_classify(ctx, dev, f)
