@@ -82,30 +82,35 @@ def main():
     codes = torch.zeros(shape, dtype=torch.uint8, device=dev)
     crit = torch.empty(cap, dtype=torch.int32, device=dev)
 
-    def step():
-        return pc.progressive(ft, ctx=ctx, capacity=cap, codes=codes, crit=crit)
+    def step(level_times=False):
+        return pc.progressive(ft, ctx=ctx, capacity=cap, codes=codes, crit=crit,
+                              level_times=level_times)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    # timed region A: the whole hot path, no per-kernel events
-    lvl_ms = []
+    # timed region A: the whole hot path, no events inside
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = step()
-        lvl_ms.append(r.level_ms.copy())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     assert r.status == 0
     ms_per_step = elapsed * 1e3 / args.steps
     value = total_v / (ms_per_step * 1e-3) / 1e9
+
+    # region T: the same steps with a completion event per launch; time to
+    # exact = first kernel to level-0 completion (stream events)
+    lvl_ms = []
+    for _ in range(args.steps):
+        lvl_ms.append(step(level_times=True).level_ms.copy())
     lvl_ms = np.array(lvl_ms)
     t_exact = float(np.median(lvl_ms[:, -1]))
 
-    # timed region B: the same steps with HIP events around the level-0
-    # kernels (on the stream they run on), for the dominant kernel's duration
+    # timed region B: HIP events around the level-0 kernels (on the stream
+    # they run on), for the dominant kernel's duration
     ctx.set_kernel_timing([0])
     k0 = []
     torch.cuda.synchronize()
@@ -116,9 +121,9 @@ def main():
     torch.cuda.synchronize()
     k0 = np.array(k0)
 
-    # one pass with every level timed, for the per-level breakdown
+    # passes with every launch timed, for the per-level breakdown (levels
+    # that share a launch are timed together under the finest of them)
     ctx.set_kernel_timing(True)
-    per_level = {}
     cls_ms, cmp_ms = [], []
     for _ in range(5):
         step()
@@ -128,11 +133,21 @@ def main():
     ctx.set_kernel_timing(None)
     cls_ms = np.median(np.array(cls_ms), axis=0)
     cmp_ms = np.median(np.array(cmp_ms), axis=0)
+    per_level = {}
+    pending = []
     for k in levels:
+        pending.append(k)
         c, m = float(cls_ms[k]), float(cmp_ms[k])
-        per_level[str(k)] = {"vertices": sizes[k], "classify_us": round(c * 1e3, 2),
-                             "compact_us": round(m * 1e3, 2),
-                             "gvps": round(sizes[k] / ((c + m) * 1e-3) / 1e9, 2)}
+        if c < 0:
+            continue  # shares the launch of a finer level
+        nv = sum(sizes[j] for j in pending)
+        e = {"vertices": nv, "classify_us": round(c * 1e3, 2),
+             "compact_us": round(m * 1e3, 2),
+             "gvps": round(nv / ((c + m) * 1e-3) / 1e9, 2)}
+        if len(pending) > 1:
+            e["levels"] = list(pending)
+        per_level[str(k)] = e
+        pending = []
 
     # dominant kernel: level-0 classification (progressive)
     k0_ms = float(np.mean(k0[:, 0]))
@@ -191,6 +206,7 @@ def main():
             "critical_fraction_level0": round(d.count / sizes[0], 4),
         },
         "time_to_exact_ms": round(t_exact, 4),
+        "level_done_ms": {str(k): round(float(v), 4) for k, v in zip(levels, med_lvl)},
         "preview_f1_at_10pct": round(f1, 4),
         "preview_level_at_10pct": kprev,
         "direct_level0_gvps": round(sizes[0] / (direct_ms * 1e-3) / 1e9, 2),

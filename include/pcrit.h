@@ -116,7 +116,7 @@ int pcrit_link_table(int dim, uint8_t *table_host, int64_t size);
  *                    written; codes are complete)
  *   crit_count_dev   device int64 or NULL; if set, the count is written
  *                    there asynchronously (no synchronisation); it is set to
- *                    -1 if a NaN was found and to -2 on an internal error.
+ *                    -1 if a NaN was found.
  * With crit_count_host == NULL the call does not synchronise, and
  * PCRIT_E_NAN / PCRIT_E_CAPACITY can only be observed through
  * crit_count_dev.  The result does not depend on the launch configuration:
@@ -150,11 +150,17 @@ typedef void (*pcrit_level_cb)(int level, int64_t count, void *user);
  *                 is crit[off[i] .. off[i+1]) with i = k_max - k
  *   level_ms_host host, k_max+1 entries or NULL: milliseconds from the first
  *                 enqueued kernel to the completion of level k, at index
- *                 i = k_max - k (stream-event timing)
+ *                 i = k_max - k (stream-event timing; NULL records no
+ *                 events).  Levels whose work shares one launch (see below)
+ *                 report the same time
  *   reclassified_host  host, k_max+1 entries or NULL: number of old vertices
  *                 re-classified at each level (index i; 0 for level k_max)
  *   cb, user      optional per-level callback (forces a synchronisation per
  *                 level)
+ * Levels of at most 2^22 vertices are latency bound: unless cb is set, the
+ * leading run of such levels (up to 16) is classified in one launch and
+ * compacted in one more; their old vertices are then tested against the
+ * previous level's masks recomputed from the field, with the same result.
  * The call always synchronises the stream at its end.  Returns
  * PCRIT_E_CAPACITY (offsets still report the required sizes) or
  * PCRIT_E_NAN as pcrit_classify does. */
@@ -171,8 +177,9 @@ int pcrit_progressive(pcrit_ctx *ctx, void *hip_stream, const float *field,
  * add a few microseconds of stream time each).  pcrit_kernel_ms then
  * returns, for the most recent call, the durations in milliseconds of the
  * classification and of the compaction of each level (index = level, up to
- * max_levels entries each; -1 where nothing was timed).  It synchronises on
- * the last recorded event. */
+ * max_levels entries each; -1 where nothing was timed).  Levels that share a
+ * launch are timed as one, under the finest of them (the others read -1).
+ * It synchronises on the last recorded event. */
 int pcrit_set_kernel_timing(pcrit_ctx *ctx, uint64_t level_mask);
 int pcrit_kernel_ms(pcrit_ctx *ctx, float *classify_ms_host,
                     float *compact_ms_host, int max_levels);

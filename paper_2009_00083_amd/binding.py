@@ -258,7 +258,7 @@ class ProgressiveResult:
     crit_codes: "object"
     levels: List[int]           # k_max .. 0
     offsets: np.ndarray         # k_max + 2 entries
-    level_ms: np.ndarray        # cumulative ms at each level's completion
+    level_ms: Optional[np.ndarray]  # ms to each level's completion, or None
     reclassified: np.ndarray    # old vertices re-classified per level
     status: int
 
@@ -274,8 +274,13 @@ class ProgressiveResult:
 def progressive(field, *, ctx: Optional[Context] = None,
                 capacity: Optional[int] = None, with_crit_codes: bool = False,
                 codes=None, crit=None, crit_codes=None, stream=None,
-                callback=None, check: bool = True) -> ProgressiveResult:
-    """Coarse-to-fine classification over every level of the hierarchy."""
+                callback=None, level_times: bool = False,
+                check: bool = True) -> ProgressiveResult:
+    """Coarse-to-fine classification over every level of the hierarchy.
+
+    With ``level_times`` the result carries the stream time from the first
+    kernel to each level's completion (level_ms); without, no events are
+    recorded and level_ms is None."""
     import torch
     nx, ny, nz = _check_field(field)
     lib = _load()
@@ -295,13 +300,14 @@ def progressive(field, *, ctx: Optional[Context] = None,
         crit_codes = torch.empty(max(capacity, 1), dtype=torch.uint8,
                                  device=field.device)
     offs = np.zeros(kmax + 2, np.int64)
-    ms = np.zeros(kmax + 1, np.float32)
+    ms = np.zeros(kmax + 1, np.float32) if level_times else None
     rec = np.zeros(kmax + 1, np.int64)
     cb = lib.LEVEL_CB(callback) if callback else ctypes.cast(None, lib.LEVEL_CB)
     st = lib.pcrit_progressive(
         c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
         _ptr(codes), _ptr(crit), _ptr(crit_codes), int(capacity),
-        offs.ctypes.data, ms.ctypes.data, rec.ctypes.data, cb, None)
+        offs.ctypes.data, None if ms is None else ms.ctypes.data,
+        rec.ctypes.data, cb, None)
     if check and st not in (0, E_CAPACITY):
         raise PcritError(st, "pcrit_progressive")
     return ProgressiveResult(codes, crit, crit_codes,

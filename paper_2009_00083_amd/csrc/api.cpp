@@ -31,6 +31,9 @@ int check_dims(int64_t nx, int64_t ny, int64_t nz) {
     return PCRIT_E_DIMS;
   const double n = (double)nx * (double)ny * (double)nz;
   if (n > 4294967295.0) return PCRIT_E_DIMS;
+  // the kernels address a plane (3D) or a row (2D) with 32-bit byte offsets
+  if ((nz > 1 ? (double)nx * (double)ny : (double)nx) > 1073741824.0)
+    return PCRIT_E_DIMS;
   return PCRIT_OK;
 }
 
@@ -55,7 +58,7 @@ int make_geom(int64_t nx, int64_t ny, int64_t nz, int level, Geom *g) {
   g->mx = (nx - 1) / g->s + 1;
   g->my = (ny - 1) / g->s + 1;
   g->mz = g->dim == 3 ? (nz - 1) / g->s + 1 : 1;
-  g->rowwords = (g->mx + 63) / 64;
+  g->rowwords = (g->mx + kTileOut - 1) / kTileOut;
   g->rows = g->my * g->mz;
   g->words = g->rows * g->rowwords;
   return PCRIT_OK;
@@ -330,9 +333,12 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   if (hipSetDevice(hip_device) != hipSuccess) return PCRIT_E_HIP;
   pcrit_ctx *c = new pcrit_ctx();
   c->device = hip_device;
-  uint8_t h3[kLut3Size], h2[kLut2Size];
-  build_link_table3(h3);
-  build_link_table2(h2);
+  // device tables are indexed by raw masks (true mask ^ kPos)
+  uint8_t t3[kLut3Size], t2[kLut2Size], h3[kLut3Size], h2[kLut2Size];
+  build_link_table3(t3);
+  build_link_table2(t2);
+  for (int i = 0; i < kLut3Size; i++) h3[i] = t3[i ^ kPos3];
+  for (int i = 0; i < kLut2Size; i++) h2[i] = t2[i ^ kPos2];
   bool ok = hipMalloc(&c->lut3, kLut3Size) == hipSuccess &&
             hipMalloc(&c->lut2, kLut2Size) == hipSuccess &&
             hipMalloc(&c->status, kStatusBytes) == hipSuccess &&
@@ -499,15 +505,18 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
 
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
-  if (hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
+  // Completion events only when asked for: every record is a release on the
+  // stream, which costs microseconds of GPU time.  Levels of one launch
+  // complete together and share the event of its last level.
+  const bool timed = level_ms_host != nullptr;
+  if (timed && hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
     st = enqueue_group(c, s, field, &steps[i], n, codes, crit, crit_codes,
                        crit_capacity, nullptr, gen);
     if (st) return st;
-    // levels of one launch complete together
-    for (int j = i; j < i + n; j++)
-      if (hipEventRecord(c->ev_level[j], s) != hipSuccess) return PCRIT_E_HIP;
+    if (timed && hipEventRecord(c->ev_level[i + n - 1], s) != hipSuccess)
+      return PCRIT_E_HIP;
     if (cb) {
       if (read_status(c, s)) return PCRIT_E_HIP;
       cb(kmax - i, c->h_base[i + 1] - c->h_base[i], user);
@@ -519,12 +528,13 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   if (reclassified_host)
     for (int i = 0; i <= kmax; i++)
       reclassified_host[i] = i == 0 ? 0 : (int64_t)c->h_flags[3 + i];
-  if (level_ms_host)
-    for (int i = 0; i <= kmax; i++) {
+  if (timed)
+    for (int i = 0; i <= kmax; i = group_end[i]) {
       float ms = -1.f;
-      if (hipEventElapsedTime(&ms, c->ev_start, c->ev_level[i]) != hipSuccess)
+      if (hipEventElapsedTime(&ms, c->ev_start, c->ev_level[group_end[i] - 1]) !=
+          hipSuccess)
         ms = -1.f;
-      level_ms_host[i] = ms;
+      for (int j = i; j < group_end[i]; j++) level_ms_host[j] = ms;
     }
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
   return c->h_base[kmax + 1] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;

@@ -1,58 +1,61 @@
 // Classification and compaction kernels for gfx950 (MI355X).
 //
 // classify3d / classify2d: per-vertex critical-point classification of one
-// level of the hierarchy (wave tiles marched along the slowest axis, see
-// below); the result per vertex is a code byte and a bit of the level's
-// critical bitmask.
+// level of the hierarchy, or of several small levels in one launch (wave
+// tiles marched along the slowest axis, see below); the result per vertex is
+// a code byte and a bit of the level's critical bitmask.
 //
 // count/expand: turn the per-level critical bitmask into the ascending list
 // of full-resolution indices; the expansion is wave-cooperative, so every
 // store instruction writes consecutive list entries.
+#include <type_traits>
+
 #include "pcrit_internal.h"
+
+// v_writelane: write a wave-uniform value into one lane of a register (the
+// LLVM intrinsic, bound by name).
+extern "C" __device__ int pcrit_writelane(int value, int lane, int old)
+    __asm("llvm.amdgcn.writelane.i32");
 
 namespace pcrit {
 namespace {
 
 // Hardware hands consecutive workgroups to the 8 XCDs round-robin; renumber
 // them so that each XCD (and its L2) gets a contiguous run of tiles, whose
-// halos it then shares.
+// halo rows it then shares.
 __device__ __forceinline__ int xcd_block_id() {
   const int G = gridDim.x, b = blockIdx.x;
   const int q = G >> 3, r = G & 7, xcd = b & 7, j = b >> 3;
   return xcd * q + min(xcd, r) + j;
 }
 
-__device__ __forceinline__ bool code_is_critical(unsigned code) {
-  // regular iff lower == 1, upper == 1 and no hole flag (bit 7); bit 6
-  // (boundary) does not matter
-  return (code & 0xBFu) != 0x09u;
-}
-
-// Boundary vertex with absent-neighbour mask A != 0.  The link in the domain
-// is the part of the full neighbour link spanned by the present neighbours.
-// Forcing the absent ones to "upper" leaves the lower link as the 0-bits;
-// the 1-bits are then the complement of the lower link in the full link
-// sphere, whose component count minus one is the lower link's number of
-// holes (Alexander duality on the 2-sphere).  Symmetrically for the upper
-// link with the absent neighbours forced to "lower".
+// Boundary vertex with absent-neighbour mask A != 0 and raw mask mr (the
+// table is indexed by raw masks, true mask = raw ^ kPos).  The link in the
+// domain is the part of the full neighbour link spanned by the present
+// neighbours.  Forcing the absent ones to "upper" leaves the lower link as
+// the 0-bits; the 1-bits are then the complement of the lower link in the
+// full link sphere, whose component count minus one is the lower link's
+// number of holes (Alexander duality on the 2-sphere).  Symmetrically for
+// the upper link with the absent neighbours forced to "lower".
 __device__ __forceinline__ unsigned boundary_code3(const uint8_t *lut,
-                                                   unsigned m, unsigned A) {
-  const unsigned eL = lut[m | A];
-  const unsigned eU = lut[m & ~A & 0x3FFFu];
+                                                   unsigned mr, unsigned A) {
+  const unsigned eL = lut[(mr & ~A) | (~kPos3 & A)];  // true mask | A
+  const unsigned eU = lut[(mr & ~A) | (kPos3 & A)];   // true mask & ~A
   const unsigned holes = ((eL >> 3) > 1u) | ((eU & 7u) > 1u);
   return (eL & 7u) | (eU & 0x38u) | 0x40u | (holes << 7);
 }
 
 // In 2D the link is a path at the boundary: its parts never have holes.
 __device__ __forceinline__ unsigned boundary_code2(const uint8_t *lut,
-                                                   unsigned m, unsigned A) {
-  return (lut[m | A] & 7u) | (lut[m & ~A & 0x3Fu] & 0x38u) | 0x40u;
+                                                   unsigned mr, unsigned A) {
+  return (lut[(mr & ~A) | (~kPos2 & A)] & 7u) |
+         (lut[(mr & ~A) | (kPos2 & A)] & 0x38u) | 0x40u;
 }
 
-// Polarity masks.  Bit j is 1 iff neighbour j comes after the centre c in the
-// order (value, full-resolution index).  For a neighbour with a larger index
-// ("positive" offset: first non-zero of (dz, dy, dx) > 0) that is f >= c,
-// for one with a smaller index it is f > c.
+// Polarity masks by exact comparison.  Bit j is 1 iff neighbour j comes
+// after the centre c in the order (value, full-resolution index).  For a
+// neighbour with a larger index ("positive" offset: first non-zero of
+// (dz, dy, dx) > 0) that is f >= c, for one with a smaller index f > c.
 __device__ __forceinline__ unsigned mask3(float c, const float *lo,
                                           const float *mid, const float *hi) {
   // lo: (0,0) (-1,0) (0,-1) (-1,-1) of plane z-1
@@ -97,42 +100,65 @@ constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 // ---------------------------------------------------------------------------
 // Shared structure of the classification kernels
 // ---------------------------------------------------------------------------
-// * Every wave owns a tile: 64 consecutive x (one sample per lane) by R rows
-//   (3D) or one row (2D), marched along the slowest axis.  The waves of a
-//   block share only the link-pattern table, so there is no block barrier
-//   inside the march.
-// * The samples of a plane stay in registers.  The x-1 and x+1 neighbours
-//   come from the lanes next door through DPP wave shifts; lanes 0 and 63
-//   take them from a halo load of the same row.
+// * Every wave owns a tile: a window of 64 consecutive x (one sample per
+//   lane) by R rows (3D) or one row (2D), marched along the slowest axis.
+//   Lanes 1..62 are classified; lanes 0 and 63 only hold the x-1 / x+1
+//   neighbours of lanes 1 and 62.  The waves of a block share only the
+//   link-pattern table, so there is no block barrier inside the march.
+// * The samples of the planes (rows) around the current one stay in
+//   registers.  x-1 and x+1 neighbours are read from the lanes next door by
+//   a DPP wave shift that the compiler folds into the subtraction itself.
 // * A polarity bit is the sign of one float difference, appended to the mask
 //   with one alignbit.  For a centre c that is finite and non-zero the sign
-//   of c - n (or n - c) is exact, ties included; lanes whose centre is +-0,
-//   +-inf or NaN take exact comparisons instead.
-// * The march issues global loads only (planes kept three ahead).  On this
-//   architecture loads and stores share one completion counter, and with a
-//   store in flight the compiler can no longer wait for one particular load;
-//   codes and masks are therefore staged in LDS and written after the tile.
+//   of c - n (or n - c) is exact, ties included; a step in which some lane's
+//   centre is +-0, +-inf or NaN recomputes its masks by exact comparisons.
+// * Loads use a scalar plane (row) base and a 32-bit lane offset.  The march
+//   issues loads only (planes kept three ahead): on this architecture loads
+//   and stores share one completion counter, and with a store in flight the
+//   compiler can no longer wait for one particular load, so codes and masks
+//   are staged in LDS and written after the tile.
 // * Persistent blocks walk the tile list; the tiles of one XCD form a
 //   contiguous run, so neighbouring tiles (which share halo rows) meet in
 //   the same L2.  A launch may cover several small levels (the progressive
 //   driver fuses the latency-bound coarse levels); a wave then looks up the
 //   level of its tile in the launch's level table.
-constexpr int kUnroll = 6;       // march unroll: window period 3, parity 2
 constexpr uint8_t kKeep = 0xFF;  // staging: no code to write (never a code)
-constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- lane i reads lane i-1
 constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
-constexpr unsigned kPos3 = 0x3EA0u;  // mask bits of positive 3D offsets
-constexpr unsigned kPos2 = 0x2Au;    // mask bits of positive 2D offsets
+constexpr int kDppRol1 = 0x134;  // wave_rol:1 -- lane i reads lane i+1 (63: 0)
+constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- lane i reads lane i-1
+constexpr int kDppRor1 = 0x13C;  // wave_ror:1 -- lane i reads lane i-1 (0: 63)
 
-// x-1 neighbour: lane i gets lane i-1, lane 0 gets `halo` (its lane-0 value)
-__device__ __forceinline__ float from_left(float halo, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(
-      __float_as_int(halo), __float_as_int(v), kDppShr1, 0xF, 0xF, false));
+// Neighbour reads across lanes: from_right = the x+1 sample, from_left =
+// the x-1 sample.  The four forms agree on lanes 1..62 (the classified
+// ones) and differ only on the halo lanes 0 and 63.  A plane row feeds up
+// to four subtractions with the same shift; spelling each use differently
+// keeps one shift per use, which the compiler folds into the subtraction
+// as a DPP operand instead of a separate move.
+template <int F>
+__device__ __forceinline__ float from_right(float v) {
+  const int b = __float_as_int(v);
+  if (F == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppShl1, 0xF, 0xF, true));
+  if (F == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShl1, 0xF, 0xF, false));
+  if (F == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShl1, 0xF, 0xF, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppRol1, 0xF, 0xF, true));
 }
-// x+1 neighbour: lane i gets lane i+1, lane 63 gets `halo` (its lane-63 value)
-__device__ __forceinline__ float from_right(float halo, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(
-      __float_as_int(halo), __float_as_int(v), kDppShl1, 0xF, 0xF, false));
+template <int F>
+__device__ __forceinline__ float from_left(float v) {
+  const int b = __float_as_int(v);
+  if (F == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppShr1, 0xF, 0xF, true));
+  if (F == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShr1, 0xF, 0xF, false));
+  if (F == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShr1, 0xF, 0xF, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppRor1, 0xF, 0xF, true));
+}
+// Plain neighbour reads for the exact-comparison path (lanes 0 / 63 keep
+// their own value).
+__device__ __forceinline__ float nb_right(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, kDppShl1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float nb_left(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, kDppShr1, 0xF, 0xF, false));
 }
 // m << 1 | sign bit of d
 __device__ __forceinline__ unsigned push_sign(unsigned m, float d) {
@@ -142,27 +168,41 @@ __device__ __forceinline__ unsigned push_sign(unsigned m, float d) {
 __device__ __forceinline__ bool special_centre(float c) {
   return __builtin_amdgcn_classf(c, 0x3 | 0x4 | 0x200 | 0x20 | 0x40);
 }
+__device__ __forceinline__ uint64_t wave_ballot(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
+// this lane's bit of a wave mask
+__device__ __forceinline__ bool lane_bit(uint64_t m) {
+  return __builtin_amdgcn_inverse_ballot_w64(m);
+}
 
-// One plane of a wave tile: rows y0-1 .. y0+R (index i = row - y0 + 1).
-template <int R>
-struct Plane {
-  float v[R + 2];  // samples at x
-  float l[R + 2];  // samples at x-1 (rows 0..R used)
-  float r[R + 2];  // samples at x+1 (rows 1..R+1 used)
-  unsigned pm;     // previous-level masks of the even rows (progressive)
-};
+// Buffer resources: a scalar base address and a 32-bit lane offset per
+// access, so address arithmetic stays off the vector ALU.  (Raw buffer,
+// no swizzle; the record limit is the full 32-bit offset range.)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1,
+                                           0x00020000);
+}
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ unsigned ld_u16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+__device__ __forceinline__ unsigned ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+__device__ __forceinline__ void st_u8(__amdgpu_buffer_rsrc_t r, uint32_t off, unsigned v) {
+  __builtin_amdgcn_raw_buffer_store_b8((unsigned char)v, r, off, 0, 0);
+}
+__device__ __forceinline__ void st_u16(__amdgpu_buffer_rsrc_t r, uint32_t off, unsigned v) {
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, off, 0, 0);
+}
 
-template <int R>
-struct PlaneLoad {
-  float v[R + 2];
-  float h[R + 2];  // lane 0: x0-1, lane 63: x0+64, other lanes: x again
-  unsigned pm[(R + 1) / 2];
-};
-
-// Level-(k+1) polarity mask of an old vertex, from its neighbours two
-// level-k steps away (used where the previous level's masks are not
-// stored); same tie rule as the level-k mask.  Off-grid positions are
-// clamped: their bits are masked by the caller.
+// Level-(k+1) raw polarity mask of an old vertex, from its neighbours two
+// level-k steps away (for levels classified in the same launch as the
+// previous one, whose masks are then not stored).  Positions off the grid
+// are clamped: their bits are masked by the caller.
 __device__ __forceinline__ unsigned far_mask3(const float *f,
                                               const LevelDesc &g, int x,
                                               int y, int z, float c) {
@@ -177,7 +217,7 @@ __device__ __forceinline__ unsigned far_mask3(const float *f,
   const float lo[4] = {v[0], v[1], v[2], v[3]};
   const float mid[6] = {v[4], v[5], v[6], v[7], v[8], v[9]};
   const float hi[4] = {v[10], v[11], v[12], v[13]};
-  return mask3(c, lo, mid, hi);
+  return mask3(c, lo, mid, hi) ^ kPos3;
 }
 
 __device__ __forceinline__ unsigned far_mask2(const float *f,
@@ -190,30 +230,51 @@ __device__ __forceinline__ unsigned far_mask2(const float *f,
     const int yy = min(max(y + 2 * kOff2[j][1], 0), g.my - 1);
     v[j] = f[(int64_t)xx * g.sx + (int64_t)yy * g.sy];
   }
-  return mask2(c, v);
+  return mask2(c, v) ^ kPos2;
 }
 
-// Absent-neighbour mask of (x, y, z) on a level of size (mx, my, mz), and
-// the same on the next coarser level for an old vertex (its neighbours two
-// steps away: absent beyond the last even coordinate).
-__device__ __forceinline__ unsigned absent3(int x, int y, int z, int mx,
-                                            int my, int mz) {
-  return (x == 0 ? AXM3 : 0u) | (x == mx - 1 ? AXP3 : 0u) |
-         (y == 0 ? AYM3 : 0u) | (y == my - 1 ? AYP3 : 0u) |
+// Absent-neighbour bits along x of column x on a level of mx columns.
+__device__ __forceinline__ unsigned absent_x3(int x, int mx) {
+  return (x == 0 ? AXM3 : 0u) | (x == mx - 1 ? AXP3 : 0u);
+}
+__device__ __forceinline__ unsigned absent_yz3(int y, int z, int my, int mz) {
+  return (y == 0 ? AYM3 : 0u) | (y == my - 1 ? AYP3 : 0u) |
          (z == 0 ? AZM3 : 0u) | (z == mz - 1 ? AZP3 : 0u);
 }
-__device__ __forceinline__ unsigned absent2(int x, int y, int mx, int my) {
-  return (x == 0 ? AXM2 : 0u) | (x == mx - 1 ? AXP2 : 0u) |
-         (y == 0 ? AYM2 : 0u) | (y == my - 1 ? AYP2 : 0u);
+__device__ __forceinline__ unsigned absent_x2(int x, int mx) {
+  return (x == 0 ? AXM2 : 0u) | (x == mx - 1 ? AXP2 : 0u);
 }
+__device__ __forceinline__ unsigned absent_y2(int y, int my) {
+  return (y == 0 ? AYM2 : 0u) | (y == my - 1 ? AYP2 : 0u);
+}
+// Last coordinate of the next coarser level, in this level's steps.
+__device__ __forceinline__ int coarse_last(int m) { return 2 * ((m - 1) >> 1); }
 
 // ---------------------------------------------------------------------------
-// 3D: one wave tile (64 x R x zchunk) of level g.
+// 3D: one wave tile (62 columns x R rows x zchunk planes) of level g.
 //   RP:  the previous level's masks are stored (g.prev_masks)
 //   WM:  the level's masks may be stored for the next level (g.masks)
 //   FAR: the previous level's masks may be computed from the field
 // stc / stm: this wave's LDS staging for codes / masks.
 // ---------------------------------------------------------------------------
+template <int R>
+struct Plane3 {
+  float v[R + 2];      // rows y0-1 .. y0+R at this lane's column
+  unsigned pm[R / 2];  // stored previous-level raw masks, even rows (even planes)
+};
+
+// Shift forms by use: a plane row is read shifted right as "hi" (forms 0/1)
+// and as "mid" (2/3), shifted left as "mid" (0/1) and as "lo" (2/3); the
+// low bit is the parity of the row being classified.
+template <int F0>
+__device__ __forceinline__ float sh_right(float v, int j) {
+  return (j & 1) ? from_right<F0 + 1>(v) : from_right<F0>(v);
+}
+template <int F0>
+__device__ __forceinline__ float sh_left(float v, int j) {
+  return (j & 1) ? from_left<F0 + 1>(v) : from_left<F0>(v);
+}
+
 template <int R, bool RP, bool WM, bool FAR>
 __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
                                        const LevelDesc &g, int t, int lane,
@@ -221,210 +282,260 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
                                        uint16_t *stm, bool &nan_seen,
                                        unsigned &reclass) {
   constexpr int NR = R + 2;
-  constexpr int U = kUnroll;
-  const int tx = t % g.ntx, rest = t / g.ntx;
+  constexpr int U = kUnroll3;  // ring of planes z-1 .. z+4
+  static_assert(U == 6 && R % 2 == 0, "plane ring and row parity");
+  const int mx = g.mx, my = g.my, mz = g.mz;
+  const int tx = g.ntx == 1 ? 0 : t % g.ntx, rest = g.ntx == 1 ? t : t / g.ntx;
   const int ty = rest % g.nty, zc = rest / g.nty;
-  const int x0 = tx * 64, y0 = ty * R, z0 = zc * g.zchunk;
-  const int z1 = min(z0 + g.zchunk, g.mz);
-  const int x = x0 + lane;
-  const bool col = x < g.mx;
+  const int xo = tx * kTileOut;  // first classified column
+  const int x = xo - 1 + lane;   // this lane's column
+  const int y0 = ty * R, z0 = zc * g.zchunk;  // both even
+  const int z1 = min(z0 + g.zchunk, mz);
+  const bool out_lane = lane >= 1 && lane <= kTileOut && x < mx;
+  const uint64_t out_lanes = wave_ballot(out_lane);
+  const uint64_t old_lanes = wave_ballot(out_lane && !(x & 1));
+  const bool x_inner = xo > 0 && xo + kTileOut < mx;
   const bool dirty_test = (RP || FAR) && g.dirty;
+  const bool keep_clean = g.keep_clean;
   const bool store_masks = WM && g.masks != nullptr;
+  const unsigned xA = absent_x3(x, mx);
+  const int exc = coarse_last(mx), eyc = coarse_last(my), ezc = coarse_last(mz);
+  const unsigned xA2 = (x == 0 ? AXM3 : 0u) | (x == exc ? AXP3 : 0u);
+  // interior at this level and at the previous one (no absent neighbour)
+  const bool x_inner2 = xo > 0 && xo + kTileOut < min(mx, exc + 1);
 
-  // Clamped, unconditional loads (a clamped sample is never used: the
-  // absent-neighbour mask covers every off-grid position).
-  const int xc = min(x, g.mx - 1);
-  const int xh = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + 64, g.mx - 1) : xc);
-  const int64_t xoff = (int64_t)xc * g.sx, hoff = (int64_t)xh * g.sx;
-  int64_t yoff[NR];
+  // Loads: a buffer resource per plane, a 32-bit lane offset per row (a
+  // plane is < 4 GiB).
+  const int xc = min(max(x, 0), mx - 1);
+  const char *fb = reinterpret_cast<const char *>(a.f);
+  const int64_t szb = g.sz * 4;
+  uint32_t voff[NR];
 #pragma unroll
   for (int i = 0; i < NR; i++)
-    yoff[i] = (int64_t)min(max(y0 - 1 + i, 0), g.my - 1) * g.sy;
-  const int pxc = RP ? min(xc >> 1, g.pmx - 1) : 0;
-  const uint16_t *pmasks = reinterpret_cast<const uint16_t *>(g.prev_masks);
-
-  auto load = [&](int z, PlaneLoad<R> &d) {
-    const int zcl = min(max(z, 0), g.mz - 1);
-    const float *pl = a.f + (int64_t)zcl * g.sz;
+    voff[i] = (uint32_t)(((int64_t)min(max(y0 - 1 + i, 0), my - 1) * g.sy +
+                          (int64_t)xc * g.sx) * 4);
+  const char *pmb = reinterpret_cast<const char *>(g.prev_masks);
+  const int64_t pmplane = (int64_t)g.pmx * g.pmy * 2;
+  uint32_t pmoff[R / 2];
+  if (RP) {
+    const int pxc = min(xc >> 1, g.pmx - 1);
 #pragma unroll
-    for (int i = 0; i < NR; i++) {
-      d.v[i] = pl[yoff[i] + xoff];
-      d.h[i] = pl[yoff[i] + hoff];
-    }
-    if (RP) {
-      const int pz = zcl >> 1;
-#pragma unroll
-      for (int k = 0; k < (R + 1) / 2; k++) {
-        const int py = min((y0 + 2 * k) >> 1, g.pmy - 1);
-        d.pm[k] = pmasks[((int64_t)pz * g.pmy + py) * g.pmx + pxc];
-      }
-    }
+    for (int k = 0; k < R / 2; k++)
+      pmoff[k] = (uint32_t)(((int64_t)min((y0 >> 1) + k, g.pmy - 1) * g.pmx + pxc) * 2);
+  }
+  // plane z of the field / of the previous level's masks, z clamped
+  auto plane_at = [&](int z) { return fb + (int64_t)min(max(z, 0), mz - 1) * szb; };
+  auto pmplane_at = [&](int z) {
+    return pmb + (int64_t)(min(max(z, 0), mz - 1) >> 1) * pmplane;
   };
-  auto derive = [&](const PlaneLoad<R> &d, Plane<R> &p) {
+  auto load = [&](const char *pp, const char *pmp, bool even, Plane3<R> &d) {
+    const __amdgpu_buffer_rsrc_t r = rsrc(pp);
 #pragma unroll
-    for (int i = 0; i < NR; i++) p.v[i] = d.v[i];
+    for (int i = 0; i < NR; i++) d.v[i] = ld_f32(r, voff[i]);
+    if (RP && even) {
+      const __amdgpu_buffer_rsrc_t mr = rsrc(pmp);
 #pragma unroll
-    for (int i = 0; i <= R; i++) p.l[i] = from_left(d.h[i], d.v[i]);
-#pragma unroll
-    for (int i = 1; i <= R + 1; i++) p.r[i] = from_right(d.h[i], d.v[i]);
-    if (RP) {
-      unsigned pm = 0;
-#pragma unroll
-      for (int k = 0; k < (R + 1) / 2; k++) pm |= d.pm[k] << (16 * k);
-      p.pm = pm;
+      for (int k = 0; k < R / 2; k++) d.pm[k] = ld_u16(mr, pmoff[k]);
     }
   };
 
-  uint64_t wbits = 0;  // lane q holds the critical word of staged row q
+  // Tile-level interior tests (at this level and the previous one): rows
+  // y0 .. y0+R-1 and, per step, plane z.  Lanes at an x boundary of either
+  // level are fixed up separately (xb_lanes).
+  const bool tile_y_in = y0 >= 1 && y0 + R <= min(my - 1, eyc);
+  // interior planes: 1 <= z < min(mz - 1, ezc), i.e. z - 1 < z_in_n
+  const unsigned z_in_n = (unsigned)max(min(mz - 1, ezc) - 1, 0);
+  const uint64_t xb_lanes = wave_ballot(out_lane && (xA | xA2) != 0u);
 
-  // Classify the R vertices of plane z in this lane's column.
-  auto step = [&](int z, const Plane<R> &lo, const Plane<R> &mid,
-                  const Plane<R> &hi) {
+  unsigned wlo = 0, whi = 0;  // lane q: critical word of staged row q
+
+  // Classify the R vertices of plane z (parity `even`) in this lane's column;
+  // their staged rows start at qb.
+  auto step = [&](int z, bool even, int qb, const Plane3<R> &lo,
+                  const Plane3<R> &mid, const Plane3<R> &hi) {
     const bool zlive = z < z1;
+    const bool z_inner = z > 0 && z < mz - 1;
+    unsigned mr[R];
 #pragma unroll
     for (int j = 0; j < R; j++) {
       const int i = j + 1;
-      const int y = y0 + j;
-      const bool live = zlive && col && y < g.my;
       const float c = mid.v[i];
-      unsigned m = 0;
-      m = push_sign(m, hi.r[i + 1] - c);   // 13 (1,1,1)
-      m = push_sign(m, hi.v[i + 1] - c);   // 12 (0,1,1)
-      m = push_sign(m, hi.r[i] - c);       // 11 (1,0,1)
-      m = push_sign(m, hi.v[i] - c);       // 10 (0,0,1)
-      m = push_sign(m, mid.r[i + 1] - c);  //  9 (1,1,0)
-      m = push_sign(m, c - mid.l[i - 1]);  //  8 (-1,-1,0)
-      m = push_sign(m, mid.v[i + 1] - c);  //  7 (0,1,0)
-      m = push_sign(m, c - mid.v[i - 1]);  //  6 (0,-1,0)
-      m = push_sign(m, mid.r[i] - c);      //  5 (1,0,0)
-      m = push_sign(m, c - mid.l[i]);      //  4 (-1,0,0)
-      m = push_sign(m, c - lo.l[i - 1]);   //  3 (-1,-1,-1)
-      m = push_sign(m, c - lo.v[i - 1]);   //  2 (0,-1,-1)
-      m = push_sign(m, c - lo.l[i]);       //  1 (-1,0,-1)
-      m = push_sign(m, c - lo.v[i]);       //  0 (0,0,-1)
-      m ^= kPos3;
-      if (special_centre(c)) {
-        const float lov[4] = {lo.v[i], lo.l[i], lo.v[i - 1], lo.l[i - 1]};
-        const float midv[6] = {mid.l[i],     mid.r[i],     mid.v[i - 1],
-                               mid.v[i + 1], mid.l[i - 1], mid.r[i + 1]};
-        const float hiv[4] = {hi.v[i], hi.r[i], hi.v[i + 1], hi.r[i + 1]};
-        m = mask3(c, lov, midv, hiv);
-        nan_seen |= live && (c != c);
-      }
-      // absent neighbours, only in waves that touch the level boundary
-      const bool inner = y > 0 && y < g.my - 1 && z > 0 && z < g.mz - 1 &&
-                         x0 > 0 && x0 + 64 < g.mx;
-      const unsigned A = inner ? 0u : absent3(x, y, z, g.mx, g.my, g.mz);
-      const unsigned code = A == 0u ? (unsigned)slut[m] : boundary_code3(slut, m, A);
-      uint8_t out = live ? (uint8_t)code : kKeep;
-      if ((RP || FAR) && dirty_test && !(j & 1) && !(z & 1)) {
-        // old vertex (present at level k+1): re-classified only if its
-        // polarity mask or its set of absent neighbours changed
-        const bool old = live && !(x & 1);
-        const unsigned Af = absent3(x, y, z, g.mx, g.my, g.mz);
-        const unsigned A2 =
-            absent3(x, y, z, 2 * ((g.mx - 1) >> 1) + 1,
-                    2 * ((g.my - 1) >> 1) + 1, 2 * ((g.mz - 1) >> 1) + 1);
-        unsigned pm = 0;
-        if (RP) pm = (mid.pm >> (16 * (j >> 1))) & 0xFFFFu;
-        if (FAR && !RP && old) pm = far_mask3(a.f, g, x, y, z, c);
-        const bool dirty =
-            old && (A2 != Af || ((m ^ pm) & ~Af & 0x3FFFu) != 0u);
-        if (old && !dirty && g.keep_clean) out = kKeep;
-        reclass += (unsigned)__popcll(__ballot(dirty));
-      }
-      const int q = (z - z0) * R + j;
-      stc[q * 64 + lane] = out;
-      if (WM && store_masks) stm[q * 64 + lane] = (uint16_t)m;
-      const uint64_t bal = __ballot(live && code_is_critical(code));
-      wbits = lane == q ? bal : wbits;
+      unsigned m;
+      m = push_sign(0u, sh_right<0>(hi.v[i + 1], j) - c);  // 13 (1,1,1)
+      m = push_sign(m, hi.v[i + 1] - c);                   // 12 (0,1,1)
+      m = push_sign(m, sh_right<0>(hi.v[i], j) - c);       // 11 (1,0,1)
+      m = push_sign(m, hi.v[i] - c);                       // 10 (0,0,1)
+      m = push_sign(m, sh_right<2>(mid.v[i + 1], j) - c);  //  9 (1,1,0)
+      m = push_sign(m, c - sh_left<0>(mid.v[i - 1], j));   //  8 (-1,-1,0)
+      m = push_sign(m, mid.v[i + 1] - c);                  //  7 (0,1,0)
+      m = push_sign(m, c - mid.v[i - 1]);                  //  6 (0,-1,0)
+      m = push_sign(m, sh_right<2>(mid.v[i], j) - c);      //  5 (1,0,0)
+      m = push_sign(m, c - sh_left<0>(mid.v[i], j));       //  4 (-1,0,0)
+      m = push_sign(m, c - sh_left<2>(lo.v[i - 1], j));    //  3 (-1,-1,-1)
+      m = push_sign(m, c - lo.v[i - 1]);                   //  2 (0,-1,-1)
+      m = push_sign(m, c - sh_left<2>(lo.v[i], j));        //  1 (-1,0,-1)
+      m = push_sign(m, c - lo.v[i]);                       //  0 (0,0,-1)
+      mr[j] = m;
     }
+    // Rare: a centre whose differences may not carry the order.  The branch
+    // is wave-uniform, so every lane takes part in the neighbour shifts.
+    bool sp = false;
+#pragma unroll
+    for (int j = 0; j < R; j++) sp |= special_centre(mid.v[j + 1]);
+    if (wave_ballot(sp)) {
+#pragma unroll
+      for (int j = 0; j < R; j++) {
+        const int i = j + 1;
+        const float c = mid.v[i];
+        const float lov[4] = {lo.v[i], nb_left(lo.v[i]), lo.v[i - 1],
+                              nb_left(lo.v[i - 1])};
+        const float midv[6] = {nb_left(mid.v[i]),     nb_right(mid.v[i]),
+                               mid.v[i - 1],          mid.v[i + 1],
+                               nb_left(mid.v[i - 1]), nb_right(mid.v[i + 1])};
+        const float hiv[4] = {hi.v[i], nb_right(hi.v[i]), hi.v[i + 1],
+                              nb_right(hi.v[i + 1])};
+        const unsigned ex = mask3(c, lov, midv, hiv) ^ kPos3;
+        mr[j] = special_centre(c) ? ex : mr[j];
+        nan_seen |= zlive && y0 + j < my && out_lane && (c != c);
+      }
+    }
+    // Per row: code, critical bit, dirty test.  IN: all rows of the step are
+    // interior in y and z at both levels (only x-boundary lanes differ).
+    auto rows = [&](auto in_tag) __attribute__((always_inline)) {
+      constexpr bool IN = decltype(in_tag)::value;
+#pragma unroll
+      for (int j = 0; j < R; j++) {
+        const int y = y0 + j;
+        unsigned code;
+        uint64_t crit;
+        if (IN) {
+          code = slut[mr[j]];
+          if (xb_lanes != 0ull) {
+            if (lane_bit(xb_lanes) && xA != 0u) code = boundary_code3(slut, mr[j], xA);
+            crit = wave_ballot((code & 0xBFu) != 0x09u);
+          } else {
+            crit = wave_ballot(code != 0x09u);
+          }
+        } else {
+          const bool inner = x_inner && z_inner && y > 0 && y < my - 1;
+          if (inner) {
+            code = slut[mr[j]];
+            crit = wave_ballot(code != 0x09u);
+          } else {
+            const unsigned A = xA | absent_yz3(y, z, my, mz);
+            code = A != 0u ? boundary_code3(slut, mr[j], A) : (unsigned)slut[mr[j]];
+            crit = wave_ballot((code & 0xBFu) != 0x09u);
+          }
+        }
+        unsigned out = code;
+        if ((RP || FAR) && even && !(j & 1) && dirty_test) {
+          // old vertex (present at level k+1): re-classified only if its
+          // polarity mask or its set of absent neighbours changed
+          unsigned pm = 0;
+          if (RP) pm = mid.pm[j >> 1];
+          if (FAR && !RP && out_lane && !(x & 1))
+            pm = far_mask3(a.f, g, x, y, z, mid.v[j + 1]);
+          bool d;
+          if (IN) {
+            d = mr[j] != pm;  // both are 14-bit masks
+            if (xb_lanes != 0ull && lane_bit(xb_lanes))
+              d = xA2 != xA || ((mr[j] ^ pm) & ~xA & 0x3FFFu) != 0u;
+          } else {
+            const unsigned Af = xA | absent_yz3(y, z, my, mz);
+            const unsigned A2 = xA2 | (y == 0 ? AYM3 : 0u) | (y == eyc ? AYP3 : 0u) |
+                                (z == 0 ? AZM3 : 0u) | (z == ezc ? AZP3 : 0u);
+            d = A2 != Af || ((mr[j] ^ pm) & ~Af & 0x3FFFu) != 0u;
+          }
+          const uint64_t old = (zlive && y < my) ? old_lanes : 0ull;
+          const uint64_t dm = wave_ballot(d) & old;
+          if (keep_clean) out = lane_bit(old & ~dm) ? (unsigned)kKeep : out;
+          reclass += (unsigned)__popcll(dm);
+        }
+        const int q = qb + j;
+        stc[q * 64 + lane] = (uint8_t)out;
+        if (WM && store_masks) stm[q * 64 + lane] = (uint16_t)mr[j];
+        wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
+        whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
+      }
+    };
+    if (tile_y_in && (unsigned)(z - 1) < z_in_n)
+      rows(std::true_type{});
+    else
+      rows(std::false_type{});
   };
 
-  // Prologue: planes z0-1, z0 derived; z0+1 .. z0+3 in flight.
-  Plane<R> W[3];
-  PlaneLoad<R> pf[3];
-  {
-    PlaneLoad<R> d0, d1;
-    load(z0 - 1, d0);
-    load(z0, d1);
+  // Prologue: planes z0-1 .. z0+3 in flight; plane z sits in slot
+  // (z - z0 + 1) % 6, and step z loads plane z+4 into the slot of z-2.
+  Plane3<R> W[U];
 #pragma unroll
-    for (int s = 0; s < 3; s++) load(z0 + 1 + s, pf[s]);
-    derive(d0, W[0]);
-    derive(d1, W[1]);
-  }
+  for (int s = 0; s < U - 1; s++)
+    load(plane_at(z0 - 1 + s), pmplane_at(z0 - 1 + s), (s & 1) != 0, W[s]);
+  // running pointers to plane zn = z+4 (clamped to the last plane)
+  const char *pn = plane_at(z0 + 4);
+  const char *pmn = pmplane_at(z0 + 4);
+  int zn = z0 + 4;
   // zchunk is a multiple of U; a short last tile runs up to U-1 extra steps
   // whose staged rows are never written out.
   for (int zb = z0; zb < z1; zb += U) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int z = zb + u;
-      derive(pf[u % 3], W[(u + 2) % 3]);  // plane z+1
-      load(z + 4, pf[u % 3]);
-      step(z, W[u % 3], W[(u + 1) % 3], W[(u + 2) % 3]);
+      load(pn, pmn, !(u & 1), W[(u + 5) % U]);
+      if (zn < mz - 1) {
+        pn += szb;
+        if (u & 1) pmn += pmplane;  // plane zn+1 is even
+      }
+      zn++;
+      step(z, !(u & 1), (z - z0) * R, W[u % U], W[(u + 1) % U], W[(u + 2) % U]);
     }
   }
 
-  // Write the staged tile.  Rows of a full-width tile at stride 1 leave as
-  // dwords (16 lanes per 64-byte row); rows that may hold a kept code,
-  // partial tiles and strided levels byte by byte.
+  // Write the staged tile: per row a buffer resource at the row's start and
+  // the lane's offset.
   const int nrows = (z1 - z0) * R;
+  const uint64_t wbits = (((uint64_t)whi << 32) | wlo) & out_lanes;
+  {
+    const int q = lane;
+    const int y = y0 + q % R, z = z0 + q / R;
+    if (q < nrows && y < my)
+      g.bits[((int64_t)z * my + y) * g.rowwords + tx] = wbits;
+  }
+  if (!out_lane) return;
   if (g.write_codes) {
-    const bool wide = g.sx == 1 && x0 + 64 <= g.mx && (g.sy & 3) == 0 &&
-                      ((uintptr_t)a.codes & 3) == 0;
-    auto row_needs_bytes = [&](int q) {
-      const int z = z0 + q / R, j = q % R;
-      return !wide || (g.keep_clean && !(z & 1) && !(j & 1));
-    };
-    for (int qb = 0; qb < nrows; qb += 4) {
-      const int q = qb + (lane >> 4), part = lane & 15;
-      const int y = y0 + q % R, z = z0 + q / R;
-      if (q < nrows && y < g.my && !row_needs_bytes(q)) {
-        const uint32_t v4 = *reinterpret_cast<const uint32_t *>(stc + q * 64 + part * 4);
-        *reinterpret_cast<uint32_t *>(a.codes + (int64_t)z * g.sz +
-                                      (int64_t)y * g.sy + x0 + part * 4) = v4;
-      }
-    }
+    const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
     for (int q = 0; q < nrows; q++) {
-      const int y = y0 + q % R, z = z0 + q / R;
-      if (y < g.my && row_needs_bytes(q)) {
-        const uint8_t b = stc[q * 64 + lane];
-        if (b != kKeep)
-          a.codes[(int64_t)z * g.sz + (int64_t)y * g.sy + (int64_t)x * g.sx] = b;
-      }
+      const int j = q % R, z = z0 + q / R, y = y0 + j;
+      if (y >= my) continue;
+      const unsigned b = stc[q * 64 + lane];
+      const __amdgpu_buffer_rsrc_t r =
+          rsrc(a.codes + (int64_t)z * g.sz + (int64_t)y * g.sy);
+      if (!(keep_clean && !(z & 1) && !(j & 1)) || b != kKeep) st_u8(r, xoffc, b);
     }
   }
   if (g.lcodes) {
     for (int q = 0; q < nrows; q++) {
       const int y = y0 + q % R, z = z0 + q / R;
-      if (y < g.my && col)
-        g.lcodes[((int64_t)z * g.my + y) * g.mx + x] = stc[q * 64 + lane];
+      if (y < my)
+        st_u8(rsrc(g.lcodes + ((int64_t)z * my + y) * mx), (uint32_t)x, stc[q * 64 + lane]);
     }
   }
-  {
-    const int y = y0 + lane % R, z = z0 + lane / R;
-    if (lane < nrows && y < g.my)
-      g.bits[((int64_t)z * g.my + y) * g.rowwords + tx] = wbits;
-  }
   if (WM && store_masks) {
-    uint16_t *om = reinterpret_cast<uint16_t *>(g.masks);
+    const char *ob = reinterpret_cast<const char *>(g.masks);
     for (int q = 0; q < nrows; q++) {
       const int y = y0 + q % R, z = z0 + q / R;
-      if (y < g.my && col) om[((int64_t)z * g.my + y) * g.mx + x] = stm[q * 64 + lane];
+      if (y < my)
+        st_u16(rsrc(ob + ((int64_t)z * my + y) * mx * 2), (uint32_t)x * 2u,
+               stm[q * 64 + lane]);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// 2D: one wave tile (64 x zchunk rows) of level g, marched along y.
+// 2D: one wave tile (62 columns x zchunk rows) of level g, marched along y.
 // ---------------------------------------------------------------------------
 struct Row2 {
-  float v, l, r;
-  unsigned pm;
-};
-struct RowLoad2 {
-  float v, h;
-  unsigned pm;
+  float v;
+  unsigned pm;  // stored previous-level raw mask (even rows)
 };
 
 template <bool RP, bool WM, bool FAR>
@@ -433,125 +544,131 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
                                        const uint8_t *slut, uint8_t *stc,
                                        uint8_t *stm, bool &nan_seen,
                                        unsigned &reclass) {
-  constexpr int U = kUnroll;
-  constexpr int PF = 6;  // rows in flight
-  const int tx = t % g.ntx, yc = t / g.ntx;
-  const int x0 = tx * 64, y0 = yc * g.zchunk;
-  const int y1 = min(y0 + g.zchunk, g.my);
-  const int x = x0 + lane;
-  const bool col = x < g.mx;
+  constexpr int U = kUnroll2;  // ring of rows y-1 .. y+U-2
+  static_assert(U % 2 == 0 && U >= 6, "row ring and row parity");
+  const int mx = g.mx, my = g.my;
+  const int tx = g.ntx == 1 ? 0 : t % g.ntx, yc = g.ntx == 1 ? t : t / g.ntx;
+  const int xo = tx * kTileOut;
+  const int x = xo - 1 + lane;
+  const int y0 = yc * g.zchunk;  // even
+  const int y1 = min(y0 + g.zchunk, my);
+  const bool out_lane = lane >= 1 && lane <= kTileOut && x < mx;
+  const uint64_t out_lanes = wave_ballot(out_lane);
+  const uint64_t old_lanes = wave_ballot(out_lane && !(x & 1));
+  const bool x_inner = xo > 0 && xo + kTileOut < mx;
   const bool dirty_test = (RP || FAR) && g.dirty;
+  const bool keep_clean = g.keep_clean;
   const bool store_masks = WM && g.masks != nullptr;
-  const int xc = min(x, g.mx - 1);
-  const int xh = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + 64, g.mx - 1) : xc);
-  const int64_t xoff = (int64_t)xc * g.sx, hoff = (int64_t)xh * g.sx;
-  const int pxc = RP ? min(xc >> 1, g.pmx - 1) : 0;
-  const uint8_t *pmasks = reinterpret_cast<const uint8_t *>(g.prev_masks);
+  const unsigned xA = absent_x2(x, mx);
+  const int exc = coarse_last(mx), eyc = coarse_last(my);
+  const unsigned xA2 = (x == 0 ? AXM2 : 0u) | (x == exc ? AXP2 : 0u);
+  const bool x_inner2 = xo > 0 && xo + kTileOut < min(mx, exc + 1);
+  const int xc = min(max(x, 0), mx - 1);
+  const uint32_t xoff = (uint32_t)((int64_t)xc * g.sx * 4);
+  const char *fb = reinterpret_cast<const char *>(a.f);
+  const int64_t syb = g.sy * 4;
+  const char *pmb = reinterpret_cast<const char *>(g.prev_masks);
+  const uint32_t pmx_off = RP ? (uint32_t)min(xc >> 1, g.pmx - 1) : 0u;
 
-  auto load = [&](int y, RowLoad2 &d) {
-    const int ycl = min(max(y, 0), g.my - 1);
-    const float *row = a.f + (int64_t)ycl * g.sy;
-    d.v = row[xoff];
-    d.h = row[hoff];
-    if (RP) d.pm = pmasks[(int64_t)min(ycl >> 1, g.pmy - 1) * g.pmx + pxc];
+  auto load = [&](int y, bool even, Row2 &d) {
+    const int ycl = min(max(y, 0), my - 1);
+    d.v = ld_f32(rsrc(fb + (int64_t)ycl * syb), xoff);
+    if (RP && even)
+      d.pm = ld_u8(rsrc(pmb + (int64_t)min(ycl >> 1, g.pmy - 1) * g.pmx), pmx_off);
   };
-  auto derive = [&](const RowLoad2 &d, Row2 &p) {
-    p.v = d.v;
-    p.l = from_left(d.h, d.v);
-    p.r = from_right(d.h, d.v);
-    if (RP) p.pm = d.pm;
-  };
-  uint64_t wbits = 0;
+  unsigned wlo = 0, whi = 0;
 
-  auto step = [&](int y, const Row2 &lo, const Row2 &mid, const Row2 &hi) {
-    const bool live = y < y1 && col;
+  // A row is read shifted right as "hi" (form 0) and "mid" (1), shifted
+  // left as "mid" (0) and "lo" (1).
+  auto step = [&](int y, bool even, const Row2 &lo, const Row2 &mid,
+                  const Row2 &hi) {
     const float c = mid.v;
-    unsigned m = 0;
-    m = push_sign(m, hi.r - c);   // 5 (1,1)
-    m = push_sign(m, c - lo.l);   // 4 (-1,-1)
-    m = push_sign(m, hi.v - c);   // 3 (0,1)
-    m = push_sign(m, c - lo.v);   // 2 (0,-1)
-    m = push_sign(m, mid.r - c);  // 1 (1,0)
-    m = push_sign(m, c - mid.l);  // 0 (-1,0)
-    m ^= kPos2;
-    if (special_centre(c)) {
-      const float nb[6] = {mid.l, mid.r, lo.v, hi.v, lo.l, hi.r};
-      m = mask2(c, nb);
-      nan_seen |= live && (c != c);
+    unsigned m;
+    m = push_sign(0u, from_right<0>(hi.v) - c);  // 5 (1,1)
+    m = push_sign(m, c - from_left<1>(lo.v));    // 4 (-1,-1)
+    m = push_sign(m, hi.v - c);                  // 3 (0,1)
+    m = push_sign(m, c - lo.v);                  // 2 (0,-1)
+    m = push_sign(m, from_right<1>(mid.v) - c);  // 1 (1,0)
+    m = push_sign(m, c - from_left<0>(mid.v));   // 0 (-1,0)
+    if (wave_ballot(special_centre(c))) {
+      const float nb[6] = {nb_left(mid.v), nb_right(mid.v), lo.v, hi.v,
+                           nb_left(lo.v), nb_right(hi.v)};
+      const unsigned ex = mask2(c, nb) ^ kPos2;
+      m = special_centre(c) ? ex : m;
+      nan_seen |= y < y1 && out_lane && (c != c);
     }
-    const bool inner = y > 0 && y < g.my - 1 && x0 > 0 && x0 + 64 < g.mx;
-    const unsigned A = inner ? 0u : absent2(x, y, g.mx, g.my);
-    const unsigned code = A == 0u ? (unsigned)slut[m] : boundary_code2(slut, m, A);
-    uint8_t out = live ? (uint8_t)code : kKeep;
-    if ((RP || FAR) && dirty_test && !(y & 1)) {
-      const bool old = live && !(x & 1);
-      const unsigned Af = absent2(x, y, g.mx, g.my);
-      const unsigned A2 = absent2(x, y, 2 * ((g.mx - 1) >> 1) + 1,
-                                  2 * ((g.my - 1) >> 1) + 1);
+    const bool inner = x_inner && y > 0 && y < my - 1;
+    const unsigned yA = absent_y2(y, my);
+    unsigned code;
+    uint64_t crit;
+    if (inner) {
+      code = slut[m];
+      crit = wave_ballot(code != 0x09u);
+    } else {
+      const unsigned A = xA | yA;
+      code = A != 0u ? boundary_code2(slut, m, A) : (unsigned)slut[m];
+      crit = wave_ballot((code & 0xBFu) != 0x09u);
+    }
+    unsigned out = code;
+    if ((RP || FAR) && even && dirty_test) {
       unsigned pm = 0;
       if (RP) pm = mid.pm;
-      if (FAR && !RP && old) pm = far_mask2(a.f, g, x, y, c);
-      const bool dirty = old && (A2 != Af || ((m ^ pm) & ~Af & 0x3Fu) != 0u);
-      if (old && !dirty && g.keep_clean) out = kKeep;
-      reclass += (unsigned)__popcll(__ballot(dirty));
+      if (FAR && !RP && out_lane && !(x & 1)) pm = far_mask2(a.f, g, x, y, c);
+      uint64_t dm;
+      if (x_inner2 && y > 0 && y < min(my - 1, eyc)) {
+        dm = wave_ballot(m != pm);  // both are 6-bit masks
+      } else {
+        const unsigned Af = xA | yA;
+        const unsigned A2 = xA2 | (y == 0 ? AYM2 : 0u) | (y == eyc ? AYP2 : 0u);
+        dm = wave_ballot(A2 != Af || ((m ^ pm) & ~Af & 0x3Fu) != 0u);
+      }
+      const uint64_t old = y < y1 ? old_lanes : 0ull;
+      dm &= old;
+      if (keep_clean) out = lane_bit(old & ~dm) ? (unsigned)kKeep : out;
+      reclass += (unsigned)__popcll(dm);
     }
     const int q = y - y0;
-    stc[q * 64 + lane] = out;
+    stc[q * 64 + lane] = (uint8_t)out;
     if (WM && store_masks) stm[q * 64 + lane] = (uint8_t)m;
-    const uint64_t bal = __ballot(live && code_is_critical(code));
-    wbits = lane == q ? bal : wbits;
+    wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
+    whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
   };
 
-  Row2 W[3];
-  RowLoad2 pf[PF];
-  {
-    RowLoad2 d0, d1;
-    load(y0 - 1, d0);
-    load(y0, d1);
+  // Row y sits in slot (y - y0 + 1) % U; step y loads row y + U - 2 into
+  // the slot of row y-2.
+  Row2 W[U];
 #pragma unroll
-    for (int s = 0; s < PF; s++) load(y0 + 1 + s, pf[s]);
-    derive(d0, W[0]);
-    derive(d1, W[1]);
-  }
+  for (int s = 0; s < U - 1; s++) load(y0 - 1 + s, (s & 1) != 0, W[s]);
   for (int yb = y0; yb < y1; yb += U) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int y = yb + u;
-      derive(pf[u % PF], W[(u + 2) % 3]);
-      load(y + 1 + PF, pf[u % PF]);
-      step(y, W[u % 3], W[(u + 1) % 3], W[(u + 2) % 3]);
+      load(y + U - 2, !(u & 1), W[(u + U - 1) % U]);
+      step(y, !(u & 1), W[u % U], W[(u + 1) % U], W[(u + 2) % U]);
     }
   }
 
   const int nrows = y1 - y0;
+  const uint64_t wbits = (((uint64_t)whi << 32) | wlo) & out_lanes;
+  if (lane < nrows) g.bits[(int64_t)(y0 + lane) * g.rowwords + tx] = wbits;
+  if (!out_lane) return;
   if (g.write_codes) {
-    const bool wide = g.sx == 1 && x0 + 64 <= g.mx && (g.sy & 3) == 0 &&
-                      ((uintptr_t)a.codes & 3) == 0;
-    for (int qb = 0; qb < nrows; qb += 4) {
-      const int q = qb + (lane >> 4), part = lane & 15;
-      const int y = y0 + q;
-      if (q < nrows && wide && !(g.keep_clean && !(y & 1))) {
-        const uint32_t v4 = *reinterpret_cast<const uint32_t *>(stc + q * 64 + part * 4);
-        *reinterpret_cast<uint32_t *>(a.codes + (int64_t)y * g.sy + x0 + part * 4) = v4;
-      }
-    }
+    const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
     for (int q = 0; q < nrows; q++) {
       const int y = y0 + q;
-      if (!wide || (g.keep_clean && !(y & 1))) {
-        const uint8_t b = stc[q * 64 + lane];
-        if (b != kKeep) a.codes[(int64_t)y * g.sy + (int64_t)x * g.sx] = b;
-      }
+      const unsigned b = stc[q * 64 + lane];
+      const __amdgpu_buffer_rsrc_t r = rsrc(a.codes + (int64_t)y * g.sy);
+      if (!(keep_clean && !(y & 1)) || b != kKeep) st_u8(r, xoffc, b);
     }
   }
   if (g.lcodes) {
     for (int q = 0; q < nrows; q++)
-      if (col) g.lcodes[(int64_t)(y0 + q) * g.mx + x] = stc[q * 64 + lane];
+      st_u8(rsrc(g.lcodes + (int64_t)(y0 + q) * mx), (uint32_t)x, stc[q * 64 + lane]);
   }
-  if (lane < nrows) g.bits[(int64_t)(y0 + lane) * g.rowwords + tx] = wbits;
   if (WM && store_masks) {
-    uint8_t *om = reinterpret_cast<uint8_t *>(g.masks);
+    const char *ob = reinterpret_cast<const char *>(g.masks);
     for (int q = 0; q < nrows; q++)
-      if (col) om[(int64_t)(y0 + q) * g.mx + x] = stm[q * 64 + lane];
+      st_u8(rsrc(ob + (int64_t)(y0 + q) * mx), (uint32_t)x, stm[q * 64 + lane]);
   }
 }
 
@@ -572,9 +689,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   constexpr int NW = kWavesPerBlock;
   constexpr int R = kTile3Y;
   constexpr int ZC = kZChunk3;
-  static_assert(ZC % kUnroll == 0, "tile depth must be a multiple of the unroll");
+  static_assert(ZC % kUnroll3 == 0, "tile depth must be a multiple of the unroll");
   static_assert(ZC * R <= 64, "one critical word per lane");
-  static_assert(R % 2 == 0, "tiles start on even rows");
   __shared__ __attribute__((aligned(16))) uint8_t slut[kLut3Size];
   __shared__ __attribute__((aligned(16))) uint8_t scode[NW][ZC * R * 64];
   __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? ZC * R * 64 : 2];
@@ -600,7 +716,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
                            scode[w], smask[WM ? w : 0], nan_seen, reclass);
     if ((RP || FAR) && lane == 0 && reclass) atomicAdd(&s_reclass[l], reclass);
   }
-  if (__ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
+  if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
   __syncthreads();
   if ((RP || FAR) && tid < a.nl)
     a.reclass_part[(int64_t)blockIdx.x * kMaxFused + tid] = s_reclass[tid];
@@ -611,7 +727,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
     ClassifyArgs a) {
   constexpr int NW = kWavesPerBlock;
   constexpr int YC = kYChunk2;
-  static_assert(YC % kUnroll == 0 && YC <= 64, "tile depth");
+  static_assert(YC % kUnroll2 == 0 && YC <= 64, "tile depth");
   __shared__ uint8_t slut[kLut2Size];
   __shared__ __attribute__((aligned(16))) uint8_t scode[NW][YC * 64];
   __shared__ uint8_t smask[WM ? NW : 1][WM ? YC * 64 : 4];
@@ -632,7 +748,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
                         scode[w], smask[WM ? w : 0], nan_seen, reclass);
     if ((RP || FAR) && lane == 0 && reclass) atomicAdd(&s_reclass[l], reclass);
   }
-  if (__ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
+  if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
   __syncthreads();
   if ((RP || FAR) && tid < a.nl)
     a.reclass_part[(int64_t)blockIdx.x * kMaxFused + tid] = s_reclass[tid];
@@ -763,7 +879,7 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   int64_t yy = r % L.my, zz = r / L.my;
   const int64_t rowstep = L.s * a.nx;
   int64_t rowbase = rowstep * (yy + a.ny * zz);
-  const uint32_t lane_x = (uint32_t)(L.s * lane);
+  const uint32_t lane_x = (uint32_t)(L.s * (lane - 1));  // bit L: column L-1
   const int nw = (int)min((int64_t)64 * WPT, L.words - gw0);
   for (int i = 0; i * WPT < nw; i++) {
     int64_t off = (int64_t)readlane64((uint64_t)my_off, i);
@@ -776,12 +892,13 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
               (unsigned)(word >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)word, 0u));
           const int64_t pos = off + rank;
           if (pos < a.cap) {
-            const uint32_t idx = (uint32_t)(rowbase + L.s * (int64_t)xw * 64) + lane_x;
+            const uint32_t idx =
+                (uint32_t)(rowbase + L.s * (int64_t)xw * kTileOut) + lane_x;
             a.crit[pos] = idx;
             if (a.crit_codes) {
               if (L.lcodes)
                 a.crit_codes[pos] =
-                    L.lcodes[(yy + (int64_t)L.my * zz) * L.mx + xw * 64 + lane];
+                    L.lcodes[(yy + (int64_t)L.my * zz) * L.mx + xw * kTileOut + lane - 1];
               else
                 a.crit_codes[pos] = a.codes[idx];
             }
@@ -827,13 +944,13 @@ hipError_t launch_persistent(K kernel, const ClassifyArgs &a, hipStream_t st,
   return hipGetLastError();
 }
 
-// Tile depth along the marched axis: the deepest multiple of kUnroll (up to
+// Tile depth along the marched axis: the deepest multiple of `step` (up to
 // `cap`) that still yields enough wave tiles to fill the GPU; small levels
 // get short tiles so that their march is short.
-int tile_depth(int64_t columns, int n, int cap) {
+int tile_depth(int64_t columns, int n, int cap, int step) {
   constexpr int64_t kWantTiles = 8192;
   int d = cap;
-  while (d > kUnroll && columns * ((n + d - 1) / d) < kWantTiles) d -= kUnroll;
+  while (d > step && columns * ((n + d - 1) / d) < kWantTiles) d -= step;
   return d;
 }
 
@@ -849,16 +966,16 @@ int classify_max_blocks() {
 }
 
 void plan_level3(LevelDesc &l) {
-  l.ntx = (l.mx + 63) / 64;
+  l.ntx = (l.mx + kTileOut - 1) / kTileOut;
   l.nty = (l.my + kTile3Y - 1) / kTile3Y;
-  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, kZChunk3);
+  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, kZChunk3, kUnroll3);
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
 }
 
 void plan_level2(LevelDesc &l) {
-  l.ntx = (l.mx + 63) / 64;
+  l.ntx = (l.mx + kTileOut - 1) / kTileOut;
   l.nty = 1;
-  l.zchunk = tile_depth(l.ntx, l.my, kYChunk2);
+  l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2);
   l.ntiles = l.ntx * ((l.my + l.zchunk - 1) / l.zchunk);
 }
 

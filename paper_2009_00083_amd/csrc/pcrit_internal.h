@@ -44,14 +44,28 @@ constexpr int kCompactThreads = 256;
 constexpr int kCompactWordsPerThread = 4;
 constexpr int kChunkWords = kCompactThreads * kCompactWordsPerThread;
 
-// Tiles of the classification kernels.  Every wave owns a tile of 64
-// consecutive x (one sample per lane) by kTile3Y rows (3D) or one row (2D)
-// and marches it along the slowest axis; the waves of a block only share
-// the link-pattern table.
+// Tiles of the classification kernels.  A wave holds 64 consecutive x (one
+// sample per lane) and classifies the kTileOut columns of lanes 1..62;
+// lanes 0 and 63 only supply the x-1 / x+1 neighbours of lanes 1 and 62.
+// The tile spans kTile3Y rows (3D) or one row (2D) and is marched along the
+// slowest axis; the waves of a block only share the link-pattern table.
+// A critical-bitmask word covers the kTileOut columns of one tile row: bit
+// L (1..62) is column word*kTileOut + L - 1.
+constexpr int kTileOut = 62;
 constexpr int kWavesPerBlock = 4;
 constexpr int kTile3Y = 2;    // rows per 3D wave tile
 constexpr int kZChunk3 = 24;  // planes per 3D wave tile
 constexpr int kYChunk2 = 60;  // rows per 2D wave tile
+constexpr int kUnroll3 = 6;   // 3D march unroll (planes in registers)
+constexpr int kUnroll2 = 12;  // 2D march unroll (rows in registers)
+
+// Polarity bits of the offsets with a larger linear index (first non-zero
+// of (dz, dy, dx) positive).  The kernels build a raw mask whose bit j is
+// the sign bit of the difference taken towards the larger index; the true
+// polarity mask is raw ^ kPos.  The device table is stored permuted so that
+// it is indexed by the raw mask directly.
+constexpr unsigned kPos3 = 0x3EA0u;
+constexpr unsigned kPos2 = 0x2Au;
 
 // Levels of at most kSmallLevel vertices are launch-latency bound; the
 // progressive driver classifies and compacts all of them in one launch each
