@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "noisy512"
-PMC_FILE = os.path.join(ROOT, "profiles", "classify3d_prog_noisy512_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "classify3d_level0_noisy512_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_00083_amd", "csrc", n)
                   for n in ("classify.hip", "pcrit_internal.h")]
 
@@ -38,17 +38,25 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_vertices):
+def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None if the kernel changed since."""
+    rocprofv3 counter summary ("key: value" lines), or None if the kernel
+    sources changed since the counters were taken."""
+    d = {}
     try:
         with open(PMC_FILE) as fh:
-            d = json.load(fh)
-    except (OSError, ValueError):
+            for line in fh:
+                if ":" in line and not line.startswith(("#", " ", "|")):
+                    k, v = line.split(":", 1)
+                    d[k.strip()] = v.strip()
+    except OSError:
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return int(float(d["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -59,6 +67,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=96,
                     help="level-0 z-planes of the oracle's timed sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -67,6 +78,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = 1 << 28  # float32 elements: 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 5}))
+        return
     import fieldgen
     import paper_2009_00083_amd as pc
 
@@ -153,7 +173,7 @@ def main():
     k0_ms = float(np.mean(k0[:, 0]))
     alg_bytes = 5 * sizes[0]  # 4 B field read + 1 B code write per vertex
     achieved = alg_bytes / (k0_ms * 1e-3) / 1e9
-    traffic = measured_traffic(sizes[0])
+    traffic = measured_traffic()
 
     # preview F1 at 10 % of time-to-exact (lists are deterministic, so take
     # them from one more untimed pass that also returns the codes)

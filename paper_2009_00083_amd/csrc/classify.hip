@@ -233,6 +233,20 @@ __device__ __forceinline__ unsigned far_mask2(const float *f,
   return mask2(c, v) ^ kPos2;
 }
 
+// floor(n / d) for 0 <= n < 2^31 from the divisor's multiplier and shift
+__device__ __forceinline__ int fdiv(int n, uint32_t mul, int shift) {
+  return (int)(((uint64_t)(uint32_t)n * mul) >> shift);
+}
+// tile index -> (tile column, tile row, chunk) of a level
+struct TilePos {
+  int tx, ty, zc;
+};
+__device__ __forceinline__ TilePos tile_pos(const LevelDesc &g, int t) {
+  const int rest = fdiv(t, g.ntx_mul, g.ntx_shift);
+  const int zc = fdiv(rest, g.nty_mul, g.nty_shift);
+  return {t - rest * g.ntx, rest - zc * g.nty, zc};
+}
+
 // Absent-neighbour bits along x of column x on a level of mx columns.
 __device__ __forceinline__ unsigned absent_x3(int x, int mx) {
   return (x == 0 ? AXM3 : 0u) | (x == mx - 1 ? AXP3 : 0u);
@@ -275,7 +289,22 @@ __device__ __forceinline__ float sh_left(float v, int j) {
   return (j & 1) ? from_left<F0 + 1>(v) : from_left<F0>(v);
 }
 
-template <int R, bool RP, bool WM, bool FAR>
+// Tile classes: every vertex of a tile of class 1 or 2 is interior in y
+// and z at its level and at the previous one, so the march needs no
+// boundary logic except, in class 2, for the lanes at an x boundary; other
+// tiles (class 0) take the general path.
+template <int R>
+__device__ __forceinline__ int tile_class3(const LevelDesc &g, int t) {
+  const TilePos p = tile_pos(g, t);
+  const int xo = p.tx * kTileOut, y0 = p.ty * R, z0 = p.zc * g.zchunk;
+  const int z1 = min(z0 + g.zchunk, g.mz);
+  const bool y_in = y0 >= 1 && y0 + R <= min(g.my - 1, coarse_last(g.my));
+  const bool z_in = z0 >= 1 && z1 <= min(g.mz - 1, coarse_last(g.mz));
+  const bool x_in = xo > 0 && xo + kTileOut < min(g.mx, coarse_last(g.mx) + 1);
+  return (y_in && z_in) ? (x_in ? 1 : 2) : 0;
+}
+
+template <int R, bool RP, bool WM, bool FAR, int MODE>
 __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
                                        const LevelDesc &g, int t, int lane,
                                        const uint8_t *slut, uint8_t *stc,
@@ -285,8 +314,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   constexpr int U = kUnroll3;  // ring of planes z-1 .. z+4
   static_assert(U == 6 && R % 2 == 0, "plane ring and row parity");
   const int mx = g.mx, my = g.my, mz = g.mz;
-  const int tx = g.ntx == 1 ? 0 : t % g.ntx, rest = g.ntx == 1 ? t : t / g.ntx;
-  const int ty = rest % g.nty, zc = rest / g.nty;
+  const TilePos tp = tile_pos(g, t);
+  const int tx = tp.tx, ty = tp.ty, zc = tp.zc;
   const int xo = tx * kTileOut;  // first classified column
   const int x = xo - 1 + lane;   // this lane's column
   const int y0 = ty * R, z0 = zc * g.zchunk;  // both even
@@ -339,12 +368,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     }
   };
 
-  // Tile-level interior tests (at this level and the previous one): rows
-  // y0 .. y0+R-1 and, per step, plane z.  Lanes at an x boundary of either
-  // level are fixed up separately (xb_lanes).
-  const bool tile_y_in = y0 >= 1 && y0 + R <= min(my - 1, eyc);
-  // interior planes: 1 <= z < min(mz - 1, ezc), i.e. z - 1 < z_in_n
-  const unsigned z_in_n = (unsigned)max(min(mz - 1, ezc) - 1, 0);
+  // lanes at an x boundary of this level or the previous one (class 2)
+
   const uint64_t xb_lanes = wave_ballot(out_lane && (xA | xA2) != 0u);
 
   unsigned wlo = 0, whi = 0;  // lane q: critical word of staged row q
@@ -399,8 +424,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
         nan_seen |= zlive && y0 + j < my && out_lane && (c != c);
       }
     }
-    // Per row: code, critical bit, dirty test.  IN: all rows of the step are
-    // interior in y and z at both levels (only x-boundary lanes differ).
+    // Per row: code, critical bit, dirty test.  IN: the tile is interior in
+    // y and z at both levels (only x-boundary lanes differ).
     auto rows = [&](auto in_tag) __attribute__((always_inline)) {
       constexpr bool IN = decltype(in_tag)::value;
 #pragma unroll
@@ -410,7 +435,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
         uint64_t crit;
         if (IN) {
           code = slut[mr[j]];
-          if (xb_lanes != 0ull) {
+          if (MODE == 2) {
             if (lane_bit(xb_lanes) && xA != 0u) code = boundary_code3(slut, mr[j], xA);
             crit = wave_ballot((code & 0xBFu) != 0x09u);
           } else {
@@ -438,7 +463,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
           bool d;
           if (IN) {
             d = mr[j] != pm;  // both are 14-bit masks
-            if (xb_lanes != 0ull && lane_bit(xb_lanes))
+            if (MODE == 2 && lane_bit(xb_lanes))
               d = xA2 != xA || ((mr[j] ^ pm) & ~xA & 0x3FFFu) != 0u;
           } else {
             const unsigned Af = xA | absent_yz3(y, z, my, mz);
@@ -458,10 +483,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
         whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
       }
     };
-    if (tile_y_in && (unsigned)(z - 1) < z_in_n)
-      rows(std::true_type{});
-    else
-      rows(std::false_type{});
+    rows(std::integral_constant<bool, MODE != 0>{});
   };
 
   // Prologue: planes z0-1 .. z0+3 in flight; plane z sits in slot
@@ -501,31 +523,48 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
       g.bits[((int64_t)z * my + y) * g.rowwords + tx] = wbits;
   }
   if (!out_lane) return;
+  // rows per plane that exist (the last row tile may stick out)
+  const int nyl = min(R, my - y0);
+  const int nzl = z1 - z0;
   if (g.write_codes) {
+    // full-resolution codes; plane pointer advanced per staged plane
     const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
-    for (int q = 0; q < nrows; q++) {
-      const int j = q % R, z = z0 + q / R, y = y0 + j;
-      if (y >= my) continue;
-      const unsigned b = stc[q * 64 + lane];
-      const __amdgpu_buffer_rsrc_t r =
-          rsrc(a.codes + (int64_t)z * g.sz + (int64_t)y * g.sy);
-      if (!(keep_clean && !(z & 1) && !(j & 1)) || b != kKeep) st_u8(r, xoffc, b);
+    const uint8_t *sq = stc + lane;
+    uint8_t *cp = a.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy;
+    for (int zz = 0; zz < nzl; zz++, cp += g.sz, sq += R * 64) {
+      // clean old vertices (even plane, even row) keep their code
+      const bool even_z = !(zz & 1);
+#pragma unroll
+      for (int j = 0; j < R; j++) {
+        if (j >= nyl) break;
+        const unsigned b = sq[j * 64];
+        if (!(keep_clean && even_z && !(j & 1)) || b != kKeep)
+          st_u8(rsrc(cp + (int64_t)j * g.sy), xoffc, b);
+      }
     }
   }
   if (g.lcodes) {
-    for (int q = 0; q < nrows; q++) {
-      const int y = y0 + q % R, z = z0 + q / R;
-      if (y < my)
-        st_u8(rsrc(g.lcodes + ((int64_t)z * my + y) * mx), (uint32_t)x, stc[q * 64 + lane]);
+    const uint8_t *sq = stc + lane;
+    uint8_t *lp = g.lcodes + ((int64_t)z0 * my + y0) * mx;
+    const int64_t lplane = (int64_t)my * mx;
+    for (int zz = 0; zz < nzl; zz++, lp += lplane, sq += R * 64) {
+#pragma unroll
+      for (int j = 0; j < R; j++) {
+        if (j >= nyl) break;
+        st_u8(rsrc(lp + (int64_t)j * mx), (uint32_t)x, sq[j * 64]);
+      }
     }
   }
   if (WM && store_masks) {
-    const char *ob = reinterpret_cast<const char *>(g.masks);
-    for (int q = 0; q < nrows; q++) {
-      const int y = y0 + q % R, z = z0 + q / R;
-      if (y < my)
-        st_u16(rsrc(ob + ((int64_t)z * my + y) * mx * 2), (uint32_t)x * 2u,
-               stm[q * 64 + lane]);
+    const uint16_t *sq = stm + lane;
+    char *mp = reinterpret_cast<char *>(g.masks) + (((int64_t)z0 * my + y0) * mx) * 2;
+    const int64_t mplane = (int64_t)my * mx * 2;
+    for (int zz = 0; zz < nzl; zz++, mp += mplane, sq += R * 64) {
+#pragma unroll
+      for (int j = 0; j < R; j++) {
+        if (j >= nyl) break;
+        st_u16(rsrc(mp + (int64_t)j * mx * 2), (uint32_t)x * 2u, sq[j * 64]);
+      }
     }
   }
 }
@@ -538,7 +577,16 @@ struct Row2 {
   unsigned pm;  // stored previous-level raw mask (even rows)
 };
 
-template <bool RP, bool WM, bool FAR>
+__device__ __forceinline__ int tile_class2(const LevelDesc &g, int t) {
+  const TilePos p = tile_pos(g, t);  // 2D: one tile row, chunks along y
+  const int xo = p.tx * kTileOut, y0 = p.zc * g.zchunk;
+  const int y1 = min(y0 + g.zchunk, g.my);
+  const bool y_in = y0 >= 1 && y1 <= min(g.my - 1, coarse_last(g.my));
+  const bool x_in = xo > 0 && xo + kTileOut < min(g.mx, coarse_last(g.mx) + 1);
+  return y_in ? (x_in ? 1 : 2) : 0;
+}
+
+template <bool RP, bool WM, bool FAR, int MODE>
 __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
                                        const LevelDesc &g, int t, int lane,
                                        const uint8_t *slut, uint8_t *stc,
@@ -547,7 +595,8 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   constexpr int U = kUnroll2;  // ring of rows y-1 .. y+U-2
   static_assert(U % 2 == 0 && U >= 6, "row ring and row parity");
   const int mx = g.mx, my = g.my;
-  const int tx = g.ntx == 1 ? 0 : t % g.ntx, yc = g.ntx == 1 ? t : t / g.ntx;
+  const TilePos tp = tile_pos(g, t);  // 2D: one tile row, chunks along y
+  const int tx = tp.tx, yc = tp.zc;
   const int xo = tx * kTileOut;
   const int x = xo - 1 + lane;
   const int y0 = yc * g.zchunk;  // even
@@ -562,7 +611,7 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const unsigned xA = absent_x2(x, mx);
   const int exc = coarse_last(mx), eyc = coarse_last(my);
   const unsigned xA2 = (x == 0 ? AXM2 : 0u) | (x == exc ? AXP2 : 0u);
-  const bool x_inner2 = xo > 0 && xo + kTileOut < min(mx, exc + 1);
+  const uint64_t xb_lanes = wave_ballot(out_lane && (xA | xA2) != 0u);
   const int xc = min(max(x, 0), mx - 1);
   const uint32_t xoff = (uint32_t)((int64_t)xc * g.sx * 4);
   const char *fb = reinterpret_cast<const char *>(a.f);
@@ -597,15 +646,21 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
       m = special_centre(c) ? ex : m;
       nan_seen |= y < y1 && out_lane && (c != c);
     }
-    const bool inner = x_inner && y > 0 && y < my - 1;
-    const unsigned yA = absent_y2(y, my);
     unsigned code;
     uint64_t crit;
-    if (inner) {
+    if (MODE != 0) {
+      code = slut[m];
+      if (MODE == 2) {
+        if (lane_bit(xb_lanes) && xA != 0u) code = boundary_code2(slut, m, xA);
+        crit = wave_ballot((code & 0xBFu) != 0x09u);
+      } else {
+        crit = wave_ballot(code != 0x09u);
+      }
+    } else if (x_inner && y > 0 && y < my - 1) {
       code = slut[m];
       crit = wave_ballot(code != 0x09u);
     } else {
-      const unsigned A = xA | yA;
+      const unsigned A = xA | absent_y2(y, my);
       code = A != 0u ? boundary_code2(slut, m, A) : (unsigned)slut[m];
       crit = wave_ballot((code & 0xBFu) != 0x09u);
     }
@@ -614,14 +669,17 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
       unsigned pm = 0;
       if (RP) pm = mid.pm;
       if (FAR && !RP && out_lane && !(x & 1)) pm = far_mask2(a.f, g, x, y, c);
-      uint64_t dm;
-      if (x_inner2 && y > 0 && y < min(my - 1, eyc)) {
-        dm = wave_ballot(m != pm);  // both are 6-bit masks
+      bool d;
+      if (MODE != 0) {
+        d = m != pm;  // both are 6-bit masks
+        if (MODE == 2 && lane_bit(xb_lanes))
+          d = xA2 != xA || ((m ^ pm) & ~xA & 0x3Fu) != 0u;
       } else {
-        const unsigned Af = xA | yA;
+        const unsigned Af = xA | absent_y2(y, my);
         const unsigned A2 = xA2 | (y == 0 ? AYM2 : 0u) | (y == eyc ? AYP2 : 0u);
-        dm = wave_ballot(A2 != Af || ((m ^ pm) & ~Af & 0x3Fu) != 0u);
+        d = A2 != Af || ((m ^ pm) & ~Af & 0x3Fu) != 0u;
       }
+      uint64_t dm = wave_ballot(d);
       const uint64_t old = y < y1 ? old_lanes : 0ull;
       dm &= old;
       if (keep_clean) out = lane_bit(old & ~dm) ? (unsigned)kKeep : out;
@@ -654,21 +712,20 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   if (!out_lane) return;
   if (g.write_codes) {
     const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
-    for (int q = 0; q < nrows; q++) {
-      const int y = y0 + q;
+    uint8_t *cp = a.codes + (int64_t)y0 * g.sy;
+    for (int q = 0; q < nrows; q++, cp += g.sy) {
       const unsigned b = stc[q * 64 + lane];
-      const __amdgpu_buffer_rsrc_t r = rsrc(a.codes + (int64_t)y * g.sy);
-      if (!(keep_clean && !(y & 1)) || b != kKeep) st_u8(r, xoffc, b);
+      // clean old vertices (even rows) keep their code
+      if (!(keep_clean && !(q & 1)) || b != kKeep) st_u8(rsrc(cp), xoffc, b);
     }
   }
   if (g.lcodes) {
-    for (int q = 0; q < nrows; q++)
-      st_u8(rsrc(g.lcodes + (int64_t)(y0 + q) * mx), (uint32_t)x, stc[q * 64 + lane]);
+    uint8_t *lp = g.lcodes + (int64_t)y0 * mx;
+    for (int q = 0; q < nrows; q++, lp += mx) st_u8(rsrc(lp), (uint32_t)x, stc[q * 64 + lane]);
   }
   if (WM && store_masks) {
-    const char *ob = reinterpret_cast<const char *>(g.masks);
-    for (int q = 0; q < nrows; q++)
-      st_u8(rsrc(ob + (int64_t)(y0 + q) * mx), (uint32_t)x, stm[q * 64 + lane]);
+    char *mp = reinterpret_cast<char *>(g.masks) + (int64_t)y0 * mx;
+    for (int q = 0; q < nrows; q++, mp += mx) st_u8(rsrc(mp), (uint32_t)x, stm[q * 64 + lane]);
   }
 }
 
@@ -712,8 +769,18 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   for (int t = xcd_block_id() * NW + w; t < a.ntiles; t += nwaves) {
     const int l = a.nl == 1 ? 0 : level_of_tile(a, t);
     unsigned reclass = 0;  // wave-uniform
-    tile3d<R, RP, WM, FAR>(a, a.lv[l], t - a.lv[l].tile_begin, lane, slut,
-                           scode[w], smask[WM ? w : 0], nan_seen, reclass);
+    const LevelDesc &lv = a.lv[l];
+    const int tt = t - lv.tile_begin;
+    const int cls = tile_class3<R>(lv, tt);
+    if (cls == 1)
+      tile3d<R, RP, WM, FAR, 1>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+                                nan_seen, reclass);
+    else if (cls == 2)
+      tile3d<R, RP, WM, FAR, 2>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+                                nan_seen, reclass);
+    else
+      tile3d<R, RP, WM, FAR, 0>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+                                nan_seen, reclass);
     if ((RP || FAR) && lane == 0 && reclass) atomicAdd(&s_reclass[l], reclass);
   }
   if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
@@ -744,8 +811,18 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
   for (int t = xcd_block_id() * NW + w; t < a.ntiles; t += nwaves) {
     const int l = a.nl == 1 ? 0 : level_of_tile(a, t);
     unsigned reclass = 0;
-    tile2d<RP, WM, FAR>(a, a.lv[l], t - a.lv[l].tile_begin, lane, slut,
-                        scode[w], smask[WM ? w : 0], nan_seen, reclass);
+    const LevelDesc &lv = a.lv[l];
+    const int tt = t - lv.tile_begin;
+    const int cls = tile_class2(lv, tt);
+    if (cls == 1)
+      tile2d<RP, WM, FAR, 1>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+                             nan_seen, reclass);
+    else if (cls == 2)
+      tile2d<RP, WM, FAR, 2>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+                             nan_seen, reclass);
+    else
+      tile2d<RP, WM, FAR, 0>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+                             nan_seen, reclass);
     if ((RP || FAR) && lane == 0 && reclass) atomicAdd(&s_reclass[l], reclass);
   }
   if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
@@ -970,6 +1047,8 @@ void plan_level3(LevelDesc &l) {
   l.nty = (l.my + kTile3Y - 1) / kTile3Y;
   l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, kZChunk3, kUnroll3);
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
+  fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
+  fast_divisor((uint32_t)l.nty, &l.nty_mul, &l.nty_shift);
 }
 
 void plan_level2(LevelDesc &l) {
@@ -977,6 +1056,8 @@ void plan_level2(LevelDesc &l) {
   l.nty = 1;
   l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2);
   l.ntiles = l.ntx * ((l.my + l.zchunk - 1) / l.zchunk);
+  fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
+  fast_divisor(1u, &l.nty_mul, &l.nty_shift);
 }
 
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,

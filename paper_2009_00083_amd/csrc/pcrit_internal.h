@@ -80,6 +80,9 @@ struct LevelDesc {
   int rowwords;           // ceil(mx / 64)
   int zchunk;             // planes (3D) / rows (2D) per wave tile
   int ntx, nty, ntiles;   // wave tiles along x and y (3D); x (2D); total
+  // n / ntx and n / nty for 0 <= n < 2^31 as (n * mul) >> shift
+  uint32_t ntx_mul, nty_mul;
+  int ntx_shift, nty_shift;
   int tile_begin;         // first tile of this level in a fused launch
   uint64_t *bits;         // critical bitmask, rowwords words per level row
   uint8_t *lcodes;        // dense level-local codes (fused levels) or null
@@ -138,6 +141,16 @@ struct CompactArgs {
 // Fill the launch geometry of a level (tile depth, tile counts).
 void plan_level3(LevelDesc &l);
 void plan_level2(LevelDesc &l);
+
+// Division by an invariant d in [1, 2^31): with l = ceil(log2 d),
+// shift = 31 + l and mul = ceil(2^shift / d) (< 2^32), floor(n / d) equals
+// (n * mul) >> shift for every 0 <= n < 2^31.
+inline void fast_divisor(uint32_t d, uint32_t *mul, int *shift) {
+  int l = 0;
+  while ((1ull << l) < d) l++;
+  *shift = 31 + l;
+  *mul = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
+}
 // Chunks of kChunkWords words (single level) or kFusedChunkWords (fused).
 constexpr int kFusedWordsPerThread = 1;
 constexpr int kFusedChunkWords = kCompactThreads * kFusedWordsPerThread;
