@@ -881,23 +881,53 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(CompactArgs a) {
   if (tid == 0) a.counts[chunk] = tot;
 }
 
+// expand_kernel: the chunk's words are loaded at once (WPT per thread) and
+// processed in WPT rounds of one word per thread.  In a round every thread
+// expands its word into LDS at its position (block scan of the popcounts) as
+// 16-bit entries (word << 6 | bit), then the block writes the round's
+// entries to the list with coalesced stores.  Entries are in index order
+// because words are in index order and bits are expanded low to high.
 template <int WPT>
 __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) {
-  constexpr int CW = kCompactThreads * WPT;
-  __shared__ int64_t s_red[kCompactThreads / 64];
-  __shared__ unsigned s_ured[kCompactThreads / 64];
-  __shared__ int s_wtot[kCompactThreads / 64];
+  constexpr int T = kCompactThreads;
+  constexpr int CW = T * WPT;
+  constexpr int NWV = T / 64;
+  __shared__ int64_t s_red[NWV];
+  __shared__ unsigned s_ured[NWV];
+  __shared__ int s_wtot[NWV];
+  __shared__ uint16_t s_ent[T * kTileOut];
+  __shared__ uint32_t s_row0[T];
   const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = level_of_chunk(a, chunk);
   const CompactLevel &L = a.lv[li];
   const int lchunk = chunk - L.chunk_begin;
+  const int64_t wfirst = (int64_t)lchunk * CW;
+  // this thread's words: wfirst + k*T + tid, all loads issued up front
+  uint64_t wd[WPT];
+#pragma unroll
+  for (int k = 0; k < WPT; k++) {
+    const int64_t gw = wfirst + (int64_t)k * T + tid;
+    wd[k] = gw < L.words ? L.bits[gw] : 0ull;
+  }
   // entries before this chunk, and before this chunk's level, in this launch
   int64_t part = 0, lpart = 0;
-  for (int i = tid; i < chunk; i += kCompactThreads) {
-    const int n = a.counts[i];
-    part += n;
-    lpart += i < L.chunk_begin ? n : 0;
+  {
+    constexpr int U = 8;  // counts loaded per round, independent loads
+    for (int i0 = 0; i0 < chunk; i0 += U * T) {
+      int c[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int i = i0 + u * T + tid;
+        c[u] = i < chunk ? a.counts[i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int i = i0 + u * T + tid;
+        part += c[u];
+        lpart += i < L.chunk_begin ? c[u] : 0;
+      }
+    }
   }
   const int64_t prefix = block_sum(part, s_red);
   const int64_t lprefix = block_sum(lpart, s_red);
@@ -905,93 +935,80 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   const int64_t base = a.level_base[a.lv[0].slot];
   if (lchunk == 0 && L.reclass_out) {
     unsigned r = 0;
-    for (int i = tid; i < a.reclass_blocks; i += kCompactThreads)
+    for (int i = tid; i < a.reclass_blocks; i += T)
       r += a.reclass_part[(int64_t)i * kMaxFused + li];
     r = block_sum(r, s_ured);
     if (tid == 0) *L.reclass_out = r;
   }
 
-  const int64_t wfirst = (int64_t)lchunk * CW;
-  const int64_t wthr = wfirst + (int64_t)tid * WPT;
-  uint64_t wd[WPT];
-  int cnt = 0;
+  const int64_t rowstep = L.s * a.nx;
+  const uint32_t s = (uint32_t)L.s;
+  int64_t done = 0;  // entries of this chunk written so far
 #pragma unroll
   for (int k = 0; k < WPT; k++) {
-    wd[k] = (wthr + k < L.words) ? L.bits[wthr + k] : 0ull;
-    cnt += __popcll(wd[k]);
-  }
-  int incl = cnt;
+    const int64_t gw = wfirst + (int64_t)k * T + tid;
+    uint64_t word = wd[k];
+    const int cnt = __popcll(word);
+    int incl = cnt;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int v = __shfl_up(incl, d);
-    if (lane >= d) incl += v;
-  }
-  if (lane == 63) s_wtot[w] = incl;
-  __syncthreads();
-  int64_t woff = 0, btot = 0;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    if (lane == 63) s_wtot[w] = incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kCompactThreads / 64; i++) {
-    if (i < w) woff += s_wtot[i];
-    btot += s_wtot[i];
+    for (int i = 0; i < NWV; i++) {
+      woff += i < w ? s_wtot[i] : 0;
+      tot += s_wtot[i];
+    }
+    if (word) {
+      // word gw covers columns 62*xw + (bit - 1) of level row r
+      const uint32_t r = (uint32_t)gw / (uint32_t)L.rowwords;
+      const uint32_t xw = (uint32_t)gw - r * (uint32_t)L.rowwords;
+      const uint32_t zz = r / (uint32_t)L.my, yy = r - zz * (uint32_t)L.my;
+      s_row0[tid] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
+                               L.s * ((int64_t)xw * kTileOut - 1));
+      int o = woff + incl - cnt;
+      while (word) {
+        s_ent[o++] = (uint16_t)(tid << 6 | __builtin_ctzll(word));
+        word &= word - 1;
+      }
+    }
+    __syncthreads();
+    const int64_t out0 = base + prefix + done;
+    for (int e = tid; e < tot; e += T) {
+      const int64_t pos = out0 + e;
+      if (pos < a.cap) {
+        const unsigned ent = s_ent[e];
+        const uint32_t idx = s_row0[ent >> 6] + s * (ent & 63u);
+        a.crit[pos] = idx;
+        if (a.crit_codes) {
+          if (L.lcodes) {
+            // dense level index from the full-resolution one
+            const uint32_t xf = idx % (uint32_t)a.nx, rest = idx / (uint32_t)a.nx;
+            const uint32_t yf = rest % (uint32_t)a.ny, zf = rest / (uint32_t)a.ny;
+            const int64_t lix = ((int64_t)(zf / s) * L.my + yf / s) * L.mx + xf / s;
+            a.crit_codes[pos] = L.lcodes[lix];
+          } else {
+            a.crit_codes[pos] = a.codes[idx];
+          }
+        }
+      }
+    }
+    done += tot;
+    __syncthreads();
   }
-  const int64_t my_off = base + prefix + woff + (incl - cnt);
 
   // the first chunk of a later level opens its list, the last chunk of the
   // launch closes the last one
   if (li > 0 && lchunk == 0 && tid == 0) a.level_base[L.slot] = base + prefix;
   if (chunk == a.nchunks - 1 && tid == 0) {
-    const int64_t total = prefix + btot;
+    const int64_t total = prefix + done;
     a.level_base[L.slot + 1] = base + total;
     if (a.count_dev)
       *a.count_dev = (*a.nan_flag == a.gen) ? -1 : total - lprefix;
-  }
-
-  // Wave-cooperative expansion of the wave's words, in index order: a word
-  // becomes the execution mask (its set lanes are the critical x), and its
-  // lanes write consecutive list entries with one store.
-  const int64_t gw0 = wfirst + (int64_t)w * 64 * WPT;
-  if (gw0 >= L.words) return;
-  int64_t r = gw0 / L.rowwords;
-  int xw = (int)(gw0 - r * L.rowwords);
-  int64_t yy = r % L.my, zz = r / L.my;
-  const int64_t rowstep = L.s * a.nx;
-  int64_t rowbase = rowstep * (yy + a.ny * zz);
-  const uint32_t lane_x = (uint32_t)(L.s * (lane - 1));  // bit L: column L-1
-  const int nw = (int)min((int64_t)64 * WPT, L.words - gw0);
-  for (int i = 0; i * WPT < nw; i++) {
-    int64_t off = (int64_t)readlane64((uint64_t)my_off, i);
-#pragma unroll
-    for (int k = 0; k < WPT; k++) {
-      const uint64_t word = readlane64(wd[k], i);
-      if (word) {
-        if (__builtin_amdgcn_inverse_ballot_w64(word)) {
-          const unsigned rank = __builtin_amdgcn_mbcnt_hi(
-              (unsigned)(word >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)word, 0u));
-          const int64_t pos = off + rank;
-          if (pos < a.cap) {
-            const uint32_t idx =
-                (uint32_t)(rowbase + L.s * (int64_t)xw * kTileOut) + lane_x;
-            a.crit[pos] = idx;
-            if (a.crit_codes) {
-              if (L.lcodes)
-                a.crit_codes[pos] =
-                    L.lcodes[(yy + (int64_t)L.my * zz) * L.mx + xw * kTileOut + lane - 1];
-              else
-                a.crit_codes[pos] = a.codes[idx];
-            }
-          }
-        }
-        off += __popcll(word);
-      }
-      if (++xw == L.rowwords) {
-        xw = 0;
-        if (++yy == L.my) {
-          yy = 0;
-          ++zz;
-        }
-        rowbase = rowstep * (yy + a.ny * zz);
-      }
-    }
   }
 }
 
