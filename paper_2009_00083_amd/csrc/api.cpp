@@ -58,7 +58,7 @@ int make_geom(int64_t nx, int64_t ny, int64_t nz, int level, Geom *g) {
   g->mx = (nx - 1) / g->s + 1;
   g->my = (ny - 1) / g->s + 1;
   g->mz = g->dim == 3 ? (nz - 1) / g->s + 1 : 1;
-  g->rowwords = (g->mx + kTileOut - 1) / kTileOut;
+  g->rowwords = (g->mx + kTileCols - 1) / kTileCols;
   g->rows = g->my * g->mz;
   g->words = g->rows * g->rowwords;
   return PCRIT_OK;
@@ -81,7 +81,9 @@ struct pcrit_ctx {
   int64_t lcodes_bytes = 0;
   void *masks[2] = {nullptr, nullptr};  // polarity masks, level ping-pong
   int64_t masks_bytes = 0;
-  unsigned *reclass_part = nullptr;  // per block and level: re-classified
+  // Re-classified old vertices per level of a launch: the classification
+  // adds to them, the compaction reads them and sets them back to zero.
+  unsigned *reclass_acc = nullptr;
   // One device status block read back with a single copy: level_base
   // (kMaxLevels + 2 list offsets, [0] stays 0) followed by flags ([0] nan,
   // [3 + i] re-classified old vertices of progressive step i).
@@ -185,7 +187,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   a.codes = codes;
   a.lut = dim == 3 ? c->lut3 : c->lut2;
   a.nl = n;
-  a.reclass_part = c->reclass_part;
+  a.reclass_acc = c->reclass_acc;
   a.nan_flag = &c->flags[0];
   a.gen = gen;
   CompactArgs b{};
@@ -239,11 +241,10 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   }
   a.ntiles = tiles;
   const int tlevel = steps[n - 1].g.level;  // a launch is timed as its finest level
-  int grid = 0;
   record_kernel(c, 0, tlevel, 0, st);
   const Step &s0 = steps[0];
   if (launch_classify(a, dim, !fused && s0.mask_read >= 0,
-                      !fused && s0.mask_write >= 0, st, &grid) != hipSuccess)
+                      !fused && s0.mask_write >= 0, st) != hipSuccess)
     return PCRIT_E_HIP;
   record_kernel(c, 0, tlevel, 1, st);
 
@@ -259,8 +260,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   b.nan_flag = &c->flags[0];
   b.gen = gen;
   b.counts = c->counts;
-  b.reclass_part = c->reclass_part;
-  b.reclass_blocks = grid;
+  b.reclass_acc = c->reclass_acc;
   record_kernel(c, 1, tlevel, 0, st);
   if (launch_compact(b, fused, st) != hipSuccess) return PCRIT_E_HIP;
   record_kernel(c, 1, tlevel, 1, st);
@@ -342,8 +342,7 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   bool ok = hipMalloc(&c->lut3, kLut3Size) == hipSuccess &&
             hipMalloc(&c->lut2, kLut2Size) == hipSuccess &&
             hipMalloc(&c->status, kStatusBytes) == hipSuccess &&
-            hipMalloc(&c->reclass_part, (size_t)classify_max_blocks() * kMaxFused *
-                                            sizeof(unsigned)) == hipSuccess &&
+            hipMalloc(&c->reclass_acc, kMaxFused * sizeof(unsigned)) == hipSuccess &&
             hipHostMalloc(&c->h_status, kStatusBytes) == hipSuccess;
   if (ok) {
     c->level_base = (int64_t *)c->status;
@@ -353,7 +352,8 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   }
   ok = ok && hipMemcpy(c->lut3, h3, kLut3Size, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(c->lut2, h2, kLut2Size, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemset(c->status, 0, kStatusBytes) == hipSuccess;
+       hipMemset(c->status, 0, kStatusBytes) == hipSuccess &&
+       hipMemset(c->reclass_acc, 0, kMaxFused * sizeof(unsigned)) == hipSuccess;
   ok = ok && hipEventCreate(&c->ev_start) == hipSuccess;
   for (int i = 0; ok && i <= kMaxLevels; i++)
     ok = hipEventCreate(&c->ev_level[i]) == hipSuccess;
@@ -377,7 +377,7 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->lcodes);
   hipFree(c->masks[0]);
   hipFree(c->masks[1]);
-  hipFree(c->reclass_part);
+  hipFree(c->reclass_acc);
   hipFree(c->status);
   if (c->h_status) hipHostFree(c->h_status);
   if (c->ev_start) hipEventDestroy(c->ev_start);

@@ -9,6 +9,7 @@
 // of full-resolution indices; the expansion is wave-cooperative, so every
 // store instruction writes consecutive list entries.
 #include <type_traits>
+#include <utility>
 
 #include "pcrit_internal.h"
 
@@ -123,42 +124,29 @@ constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 //   driver fuses the latency-bound coarse levels); a wave then looks up the
 //   level of its tile in the launch's level table.
 constexpr uint8_t kKeep = 0xFF;  // staging: no code to write (never a code)
-constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
-constexpr int kDppRol1 = 0x134;  // wave_rol:1 -- lane i reads lane i+1 (63: 0)
-constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- lane i reads lane i-1
-constexpr int kDppRor1 = 0x13C;  // wave_ror:1 -- lane i reads lane i-1 (0: 63)
 
-// Neighbour reads across lanes: from_right = the x+1 sample, from_left =
-// the x-1 sample.  The four forms agree on lanes 1..62 (the classified
-// ones) and differ only on the halo lanes 0 and 63.  A plane row feeds up
-// to four subtractions with the same shift; spelling each use differently
-// keeps one shift per use, which the compiler folds into the subtraction
-// as a DPP operand instead of a separate move.
-template <int F>
-__device__ __forceinline__ float from_right(float v) {
-  const int b = __float_as_int(v);
-  if (F == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppShl1, 0xF, 0xF, true));
-  if (F == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShl1, 0xF, 0xF, false));
-  if (F == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShl1, 0xF, 0xF, true));
-  return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppRol1, 0xF, 0xF, true));
+// LDS staging of a wave's tile, lane-major: lane l's staged rows are
+// contiguous at l * stride, so the flush reads four rows per dword.  The
+// stride in dwords is odd, which keeps the per-row byte writes of the 64
+// lanes in distinct banks.
+constexpr int stage_dwords(int bytes) { return ((bytes + 3) / 4) | 1; }
+constexpr int kRows3 = kZChunk3 * kTile3Y;                   // staged rows (3D)
+constexpr int kCodeStride3 = 4 * stage_dwords(kRows3);       // bytes per lane
+constexpr int kMaskStride3 = 2 * stage_dwords(2 * kRows3);   // u16 per lane
+constexpr int kCodeStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
+constexpr int kMaskStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
+constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
+constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- lane i reads lane i-1
+
+// x-1 / x+1 neighbour across lanes: lane i reads lane i-1 (i+1); lane 0
+// (63) keeps `halo`, which holds the sample left (right) of the tile.
+__device__ __forceinline__ float shift_left(float halo, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(
+      __float_as_int(halo), __float_as_int(v), kDppShr1, 0xF, 0xF, false));
 }
-template <int F>
-__device__ __forceinline__ float from_left(float v) {
-  const int b = __float_as_int(v);
-  if (F == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppShr1, 0xF, 0xF, true));
-  if (F == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShr1, 0xF, 0xF, false));
-  if (F == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, b, kDppShr1, 0xF, 0xF, true));
-  return __int_as_float(__builtin_amdgcn_mov_dpp(b, kDppRor1, 0xF, 0xF, true));
-}
-// Plain neighbour reads for the exact-comparison path (lanes 0 / 63 keep
-// their own value).
-__device__ __forceinline__ float nb_right(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, kDppShl1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float nb_left(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, kDppShr1, 0xF, 0xF, false));
+__device__ __forceinline__ float shift_right(float halo, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(
+      __float_as_int(halo), __float_as_int(v), kDppShl1, 0xF, 0xF, false));
 }
 // m << 1 | sign bit of d
 __device__ __forceinline__ unsigned push_sign(unsigned m, float d) {
@@ -247,6 +235,16 @@ __device__ __forceinline__ TilePos tile_pos(const LevelDesc &g, int t) {
   return {t - rest * g.ntx, rest - zc * g.nty, zc};
 }
 
+// Calls f(std::integral_constant<int, 0>{}) .. f(<N-1>{}).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // Absent-neighbour bits along x of column x on a level of mx columns.
 __device__ __forceinline__ unsigned absent_x3(int x, int mx) {
   return (x == 0 ? AXM3 : 0u) | (x == mx - 1 ? AXP3 : 0u);
@@ -265,7 +263,7 @@ __device__ __forceinline__ unsigned absent_y2(int y, int my) {
 __device__ __forceinline__ int coarse_last(int m) { return 2 * ((m - 1) >> 1); }
 
 // ---------------------------------------------------------------------------
-// 3D: one wave tile (62 columns x R rows x zchunk planes) of level g.
+// 3D: one wave tile (64 columns x R rows x zchunk planes) of level g.
 //   RP:  the previous level's masks are stored (g.prev_masks)
 //   WM:  the level's masks may be stored for the next level (g.masks)
 //   FAR: the previous level's masks may be computed from the field
@@ -274,19 +272,26 @@ __device__ __forceinline__ int coarse_last(int m) { return 2 * ((m - 1) >> 1); }
 template <int R>
 struct Plane3 {
   float v[R + 2];      // rows y0-1 .. y0+R at this lane's column
+  float hp;            // packed halo: lane i holds column x0-1 of row i,
+                       // lane 64-NR+i column x0+64 of row i (i < NR)
+  float l[R + 1];      // x-1 neighbour of rows 0..R
+  float r[R + 1];      // x+1 neighbour of rows 1..R+1 (r[k]: row k+1)
   unsigned pm[R / 2];  // stored previous-level raw masks, even rows (even planes)
 };
 
-// Shift forms by use: a plane row is read shifted right as "hi" (forms 0/1)
-// and as "mid" (2/3), shifted left as "mid" (0/1) and as "lo" (2/3); the
-// low bit is the parity of the row being classified.
-template <int F0>
-__device__ __forceinline__ float sh_right(float v, int j) {
-  return (j & 1) ? from_right<F0 + 1>(v) : from_right<F0>(v);
+// Halo of row i from a packed halo register: lane 0 receives lane i (left
+// halo), lane 63 receives lane 64-NR+i (right halo); row shifts within the
+// 16-lane DPP rows.
+template <int I>
+__device__ __forceinline__ float halo_left(float hp) {
+  if (I == 0) return hp;
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(hp), 0x100 + I, 0xF, 0xF, false));
 }
-template <int F0>
-__device__ __forceinline__ float sh_left(float v, int j) {
-  return (j & 1) ? from_left<F0 + 1>(v) : from_left<F0>(v);
+template <int I, int NR>
+__device__ __forceinline__ float halo_right(float hp) {
+  if (I == NR - 1) return hp;
+  return __int_as_float(
+      __builtin_amdgcn_mov_dpp(__float_as_int(hp), 0x110 + (NR - 1 - I), 0xF, 0xF, false));
 }
 
 // Tile classes: every vertex of a tile of class 1 or 2 is interior in y
@@ -296,11 +301,11 @@ __device__ __forceinline__ float sh_left(float v, int j) {
 template <int R>
 __device__ __forceinline__ int tile_class3(const LevelDesc &g, int t) {
   const TilePos p = tile_pos(g, t);
-  const int xo = p.tx * kTileOut, y0 = p.ty * R, z0 = p.zc * g.zchunk;
+  const int x0 = p.tx * kTileCols, y0 = p.ty * R, z0 = p.zc * g.zchunk;
   const int z1 = min(z0 + g.zchunk, g.mz);
   const bool y_in = y0 >= 1 && y0 + R <= min(g.my - 1, coarse_last(g.my));
   const bool z_in = z0 >= 1 && z1 <= min(g.mz - 1, coarse_last(g.mz));
-  const bool x_in = xo > 0 && xo + kTileOut < min(g.mx, coarse_last(g.mx) + 1);
+  const bool x_in = x0 > 0 && x0 + kTileCols < min(g.mx, coarse_last(g.mx) + 1);
   return (y_in && z_in) ? (x_in ? 1 : 2) : 0;
 }
 
@@ -316,26 +321,27 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   const int mx = g.mx, my = g.my, mz = g.mz;
   const TilePos tp = tile_pos(g, t);
   const int tx = tp.tx, ty = tp.ty, zc = tp.zc;
-  const int xo = tx * kTileOut;  // first classified column
-  const int x = xo - 1 + lane;   // this lane's column
+  const int x0 = tx * kTileCols;  // first column of the tile
+  const int x = x0 + lane;        // this lane's column
   const int y0 = ty * R, z0 = zc * g.zchunk;  // both even
   const int z1 = min(z0 + g.zchunk, mz);
-  const bool out_lane = lane >= 1 && lane <= kTileOut && x < mx;
+  const bool out_lane = x < mx;
   const uint64_t out_lanes = wave_ballot(out_lane);
   const uint64_t old_lanes = wave_ballot(out_lane && !(x & 1));
-  const bool x_inner = xo > 0 && xo + kTileOut < mx;
+  const bool x_inner = x0 > 0 && x0 + kTileCols < mx;
   const bool dirty_test = (RP || FAR) && g.dirty;
   const bool keep_clean = g.keep_clean;
   const bool store_masks = WM && g.masks != nullptr;
   const unsigned xA = absent_x3(x, mx);
   const int exc = coarse_last(mx), eyc = coarse_last(my), ezc = coarse_last(mz);
   const unsigned xA2 = (x == 0 ? AXM3 : 0u) | (x == exc ? AXP3 : 0u);
-  // interior at this level and at the previous one (no absent neighbour)
-  const bool x_inner2 = xo > 0 && xo + kTileOut < min(mx, exc + 1);
 
   // Loads: a buffer resource per plane, a 32-bit lane offset per row (a
-  // plane is < 4 GiB).
-  const int xc = min(max(x, 0), mx - 1);
+  // plane is < 4 GiB).  One packed halo load per plane fetches the columns
+  // left and right of the tile for all rows (clamped: a clamped sample is
+  // never used).
+  static_assert(NR <= 16, "packed halo within one DPP row");
+  const int xc = min(x, mx - 1);
   const char *fb = reinterpret_cast<const char *>(a.f);
   const int64_t szb = g.sz * 4;
   uint32_t voff[NR];
@@ -343,6 +349,14 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   for (int i = 0; i < NR; i++)
     voff[i] = (uint32_t)(((int64_t)min(max(y0 - 1 + i, 0), my - 1) * g.sy +
                           (int64_t)xc * g.sx) * 4);
+  uint32_t hpoff;
+  {
+    const bool left = lane < 32;
+    const int hi = left ? min(lane, NR - 1) : max(lane - (64 - NR), 0);
+    const int hx = left ? max(x0 - 1, 0) : min(x0 + 64, mx - 1);
+    hpoff = (uint32_t)(((int64_t)min(max(y0 - 1 + hi, 0), my - 1) * g.sy +
+                        (int64_t)hx * g.sx) * 4);
+  }
   const char *pmb = reinterpret_cast<const char *>(g.prev_masks);
   const int64_t pmplane = (int64_t)g.pmx * g.pmy * 2;
   uint32_t pmoff[R / 2];
@@ -361,15 +375,26 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     const __amdgpu_buffer_rsrc_t r = rsrc(pp);
 #pragma unroll
     for (int i = 0; i < NR; i++) d.v[i] = ld_f32(r, voff[i]);
+    d.hp = ld_f32(r, hpoff);
     if (RP && even) {
       const __amdgpu_buffer_rsrc_t mr = rsrc(pmp);
 #pragma unroll
       for (int k = 0; k < R / 2; k++) d.pm[k] = ld_u16(mr, pmoff[k]);
     }
   };
+  // x-1 / x+1 neighbours of a loaded plane (lane shifts, halo at the ends)
+  auto derive = [&](Plane3<R> &d) {
+    static_for<R + 1>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      d.l[i] = shift_left(halo_left<i>(d.hp), d.v[i]);
+    });
+    static_for<R + 1>([&](auto ic) {
+      constexpr int i = decltype(ic)::value + 1;
+      d.r[i - 1] = shift_right(halo_right<i, NR>(d.hp), d.v[i]);
+    });
+  };
 
   // lanes at an x boundary of this level or the previous one (class 2)
-
   const uint64_t xb_lanes = wave_ballot(out_lane && (xA | xA2) != 0u);
 
   unsigned wlo = 0, whi = 0;  // lane q: critical word of staged row q
@@ -386,24 +411,23 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
       const int i = j + 1;
       const float c = mid.v[i];
       unsigned m;
-      m = push_sign(0u, sh_right<0>(hi.v[i + 1], j) - c);  // 13 (1,1,1)
-      m = push_sign(m, hi.v[i + 1] - c);                   // 12 (0,1,1)
-      m = push_sign(m, sh_right<0>(hi.v[i], j) - c);       // 11 (1,0,1)
-      m = push_sign(m, hi.v[i] - c);                       // 10 (0,0,1)
-      m = push_sign(m, sh_right<2>(mid.v[i + 1], j) - c);  //  9 (1,1,0)
-      m = push_sign(m, c - sh_left<0>(mid.v[i - 1], j));   //  8 (-1,-1,0)
-      m = push_sign(m, mid.v[i + 1] - c);                  //  7 (0,1,0)
-      m = push_sign(m, c - mid.v[i - 1]);                  //  6 (0,-1,0)
-      m = push_sign(m, sh_right<2>(mid.v[i], j) - c);      //  5 (1,0,0)
-      m = push_sign(m, c - sh_left<0>(mid.v[i], j));       //  4 (-1,0,0)
-      m = push_sign(m, c - sh_left<2>(lo.v[i - 1], j));    //  3 (-1,-1,-1)
-      m = push_sign(m, c - lo.v[i - 1]);                   //  2 (0,-1,-1)
-      m = push_sign(m, c - sh_left<2>(lo.v[i], j));        //  1 (-1,0,-1)
-      m = push_sign(m, c - lo.v[i]);                       //  0 (0,0,-1)
+      m = push_sign(0u, hi.r[i] - c);              // 13 (1,1,1)
+      m = push_sign(m, hi.v[i + 1] - c);           // 12 (0,1,1)
+      m = push_sign(m, hi.r[i - 1] - c);           // 11 (1,0,1)
+      m = push_sign(m, hi.v[i] - c);               // 10 (0,0,1)
+      m = push_sign(m, mid.r[i] - c);              //  9 (1,1,0)
+      m = push_sign(m, c - mid.l[i - 1]);          //  8 (-1,-1,0)
+      m = push_sign(m, mid.v[i + 1] - c);          //  7 (0,1,0)
+      m = push_sign(m, c - mid.v[i - 1]);          //  6 (0,-1,0)
+      m = push_sign(m, mid.r[i - 1] - c);          //  5 (1,0,0)
+      m = push_sign(m, c - mid.l[i]);              //  4 (-1,0,0)
+      m = push_sign(m, c - lo.l[i - 1]);           //  3 (-1,-1,-1)
+      m = push_sign(m, c - lo.v[i - 1]);           //  2 (0,-1,-1)
+      m = push_sign(m, c - lo.l[i]);               //  1 (-1,0,-1)
+      m = push_sign(m, c - lo.v[i]);               //  0 (0,0,-1)
       mr[j] = m;
     }
-    // Rare: a centre whose differences may not carry the order.  The branch
-    // is wave-uniform, so every lane takes part in the neighbour shifts.
+    // Rare: a centre whose differences may not carry the order.
     bool sp = false;
 #pragma unroll
     for (int j = 0; j < R; j++) sp |= special_centre(mid.v[j + 1]);
@@ -412,13 +436,10 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
       for (int j = 0; j < R; j++) {
         const int i = j + 1;
         const float c = mid.v[i];
-        const float lov[4] = {lo.v[i], nb_left(lo.v[i]), lo.v[i - 1],
-                              nb_left(lo.v[i - 1])};
-        const float midv[6] = {nb_left(mid.v[i]),     nb_right(mid.v[i]),
-                               mid.v[i - 1],          mid.v[i + 1],
-                               nb_left(mid.v[i - 1]), nb_right(mid.v[i + 1])};
-        const float hiv[4] = {hi.v[i], nb_right(hi.v[i]), hi.v[i + 1],
-                              nb_right(hi.v[i + 1])};
+        const float lov[4] = {lo.v[i], lo.l[i], lo.v[i - 1], lo.l[i - 1]};
+        const float midv[6] = {mid.l[i],     mid.r[i - 1], mid.v[i - 1],
+                               mid.v[i + 1], mid.l[i - 1], mid.r[i]};
+        const float hiv[4] = {hi.v[i], hi.r[i - 1], hi.v[i + 1], hi.r[i]};
         const unsigned ex = mask3(c, lov, midv, hiv) ^ kPos3;
         mr[j] = special_centre(c) ? ex : mr[j];
         nan_seen |= zlive && y0 + j < my && out_lane && (c != c);
@@ -477,8 +498,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
           reclass += (unsigned)__popcll(dm);
         }
         const int q = qb + j;
-        stc[q * 64 + lane] = (uint8_t)out;
-        if (WM && store_masks) stm[q * 64 + lane] = (uint16_t)mr[j];
+        stc[lane * kCodeStride3 + q] = (uint8_t)out;
+        if (WM && store_masks) stm[lane * kMaskStride3 + q] = (uint16_t)mr[j];
         wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
         whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
       }
@@ -490,11 +511,18 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   // (z - z0 + 1) % 6, and step z loads plane z+4 into the slot of z-2.
   Plane3<R> W[U];
 #pragma unroll
-  for (int s = 0; s < U - 1; s++)
-    load(plane_at(z0 - 1 + s), pmplane_at(z0 - 1 + s), (s & 1) != 0, W[s]);
-  // running pointers to plane zn = z+4 (clamped to the last plane)
-  const char *pn = plane_at(z0 + 4);
-  const char *pmn = pmplane_at(z0 + 4);
+  for (int s = 0; s < U - 1; s++) {
+    const int zs = min(z0 - 1 + s, z1);
+    load(plane_at(zs), pmplane_at(zs), (s & 1) != 0, W[s]);
+  }
+  derive(W[0]);
+  derive(W[1]);
+  // running pointers to plane zn = z+4, clamped to plane z1 (the last one
+  // the tile reads: the plane above its last classified plane) so that the
+  // steps past the tile re-read a plane in cache instead of the next tile's
+  const int zlast = min(z1, mz - 1);
+  const char *pn = plane_at(min(z0 + 4, zlast));
+  const char *pmn = pmplane_at(min(z0 + 4, zlast));
   int zn = z0 + 4;
   // zchunk is a multiple of U; a short last tile runs up to U-1 extra steps
   // whose staged rows are never written out.
@@ -502,8 +530,9 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int z = zb + u;
+      derive(W[(u + 2) % U]);  // plane z+1
       load(pn, pmn, !(u & 1), W[(u + 5) % U]);
-      if (zn < mz - 1) {
+      if (zn < zlast) {
         pn += szb;
         if (u & 1) pmn += pmplane;  // plane zn+1 is even
       }
@@ -526,63 +555,86 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   // rows per plane that exist (the last row tile may stick out)
   const int nyl = min(R, my - y0);
   const int nzl = z1 - z0;
+  // this lane's staged codes, four rows per dword, read at once
+  constexpr int NQ = kZChunk3 * R;
+  static_assert(NQ == kRows3, "staging geometry");
+  uint32_t cw[NQ / 4];
+  {
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stc + lane * kCodeStride3);
+#pragma unroll
+    for (int k = 0; k < NQ / 4; k++) cw[k] = sp[k];
+  }
+  auto staged = [&](int q) { return (cw[q >> 2] >> (8 * (q & 3))) & 0xFFu; };
   if (g.write_codes) {
     // full-resolution codes; plane pointer advanced per staged plane
     const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
-    const uint8_t *sq = stc + lane;
     uint8_t *cp = a.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy;
-    for (int zz = 0; zz < nzl; zz++, cp += g.sz, sq += R * 64) {
-      // clean old vertices (even plane, even row) keep their code
-      const bool even_z = !(zz & 1);
+#pragma unroll
+    for (int zz = 0; zz < kZChunk3; zz++, cp += g.sz) {
+      if (zz >= nzl) break;
 #pragma unroll
       for (int j = 0; j < R; j++) {
         if (j >= nyl) break;
-        const unsigned b = sq[j * 64];
-        if (!(keep_clean && even_z && !(j & 1)) || b != kKeep)
+        const unsigned b = staged(zz * R + j);
+        // clean old vertices (even plane, even row) keep their code
+        if (!(keep_clean && !(zz & 1) && !(j & 1)) || b != kKeep)
           st_u8(rsrc(cp + (int64_t)j * g.sy), xoffc, b);
       }
     }
   }
   if (g.lcodes) {
-    const uint8_t *sq = stc + lane;
     uint8_t *lp = g.lcodes + ((int64_t)z0 * my + y0) * mx;
     const int64_t lplane = (int64_t)my * mx;
-    for (int zz = 0; zz < nzl; zz++, lp += lplane, sq += R * 64) {
+#pragma unroll
+    for (int zz = 0; zz < kZChunk3; zz++, lp += lplane) {
+      if (zz >= nzl) break;
 #pragma unroll
       for (int j = 0; j < R; j++) {
         if (j >= nyl) break;
-        st_u8(rsrc(lp + (int64_t)j * mx), (uint32_t)x, sq[j * 64]);
+        st_u8(rsrc(lp + (int64_t)j * mx), (uint32_t)x, staged(zz * R + j));
       }
     }
   }
   if (WM && store_masks) {
-    const uint16_t *sq = stm + lane;
+    // masks: two rows per dword, read in groups of NQ / 4 dwords
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stm + lane * kMaskStride3);
     char *mp = reinterpret_cast<char *>(g.masks) + (((int64_t)z0 * my + y0) * mx) * 2;
     const int64_t mplane = (int64_t)my * mx * 2;
-    for (int zz = 0; zz < nzl; zz++, mp += mplane, sq += R * 64) {
 #pragma unroll
-      for (int j = 0; j < R; j++) {
-        if (j >= nyl) break;
-        st_u16(rsrc(mp + (int64_t)j * mx * 2), (uint32_t)x * 2u, sq[j * 64]);
+    for (int h = 0; h < 2; h++) {
+#pragma unroll
+      for (int k = 0; k < NQ / 4; k++) cw[k] = sp[h * (NQ / 4) + k];
+#pragma unroll
+      for (int zl = 0; zl < kZChunk3 / 2; zl++, mp += mplane) {
+        const int zz = h * (kZChunk3 / 2) + zl;
+        if (zz >= nzl) break;
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+          if (j >= nyl) break;
+          const int ql = zl * R + j;  // row within this group
+          const unsigned m = (cw[ql >> 1] >> (16 * (ql & 1))) & 0xFFFFu;
+          st_u16(rsrc(mp + (int64_t)j * mx * 2), (uint32_t)x * 2u, m);
+        }
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// 2D: one wave tile (62 columns x zchunk rows) of level g, marched along y.
+// 2D: one wave tile (64 columns x zchunk rows) of level g, marched along y.
 // ---------------------------------------------------------------------------
 struct Row2 {
-  float v;
+  float v, h;   // sample; as loaded, lane 0: x0-1, lane 63: x0+64
+  float l, r;   // x-1 / x+1 neighbours
   unsigned pm;  // stored previous-level raw mask (even rows)
 };
 
 __device__ __forceinline__ int tile_class2(const LevelDesc &g, int t) {
   const TilePos p = tile_pos(g, t);  // 2D: one tile row, chunks along y
-  const int xo = p.tx * kTileOut, y0 = p.zc * g.zchunk;
+  const int x0 = p.tx * kTileCols, y0 = p.zc * g.zchunk;
   const int y1 = min(y0 + g.zchunk, g.my);
   const bool y_in = y0 >= 1 && y1 <= min(g.my - 1, coarse_last(g.my));
-  const bool x_in = xo > 0 && xo + kTileOut < min(g.mx, coarse_last(g.mx) + 1);
+  const bool x_in = x0 > 0 && x0 + kTileCols < min(g.mx, coarse_last(g.mx) + 1);
   return y_in ? (x_in ? 1 : 2) : 0;
 }
 
@@ -597,14 +649,14 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const int mx = g.mx, my = g.my;
   const TilePos tp = tile_pos(g, t);  // 2D: one tile row, chunks along y
   const int tx = tp.tx, yc = tp.zc;
-  const int xo = tx * kTileOut;
-  const int x = xo - 1 + lane;
+  const int x0 = tx * kTileCols;
+  const int x = x0 + lane;
   const int y0 = yc * g.zchunk;  // even
   const int y1 = min(y0 + g.zchunk, my);
-  const bool out_lane = lane >= 1 && lane <= kTileOut && x < mx;
+  const bool out_lane = x < mx;
   const uint64_t out_lanes = wave_ballot(out_lane);
   const uint64_t old_lanes = wave_ballot(out_lane && !(x & 1));
-  const bool x_inner = xo > 0 && xo + kTileOut < mx;
+  const bool x_inner = x0 > 0 && x0 + kTileCols < mx;
   const bool dirty_test = (RP || FAR) && g.dirty;
   const bool keep_clean = g.keep_clean;
   const bool store_masks = WM && g.masks != nullptr;
@@ -612,8 +664,10 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const int exc = coarse_last(mx), eyc = coarse_last(my);
   const unsigned xA2 = (x == 0 ? AXM2 : 0u) | (x == exc ? AXP2 : 0u);
   const uint64_t xb_lanes = wave_ballot(out_lane && (xA | xA2) != 0u);
-  const int xc = min(max(x, 0), mx - 1);
+  const int xc = min(x, mx - 1);
+  const int xh = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + 64, mx - 1) : xc);
   const uint32_t xoff = (uint32_t)((int64_t)xc * g.sx * 4);
+  const uint32_t hoff = (uint32_t)((int64_t)xh * g.sx * 4);
   const char *fb = reinterpret_cast<const char *>(a.f);
   const int64_t syb = g.sy * 4;
   const char *pmb = reinterpret_cast<const char *>(g.prev_masks);
@@ -621,27 +675,30 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
 
   auto load = [&](int y, bool even, Row2 &d) {
     const int ycl = min(max(y, 0), my - 1);
-    d.v = ld_f32(rsrc(fb + (int64_t)ycl * syb), xoff);
+    const __amdgpu_buffer_rsrc_t r = rsrc(fb + (int64_t)ycl * syb);
+    d.v = ld_f32(r, xoff);
+    d.h = ld_f32(r, hoff);
     if (RP && even)
       d.pm = ld_u8(rsrc(pmb + (int64_t)min(ycl >> 1, g.pmy - 1) * g.pmx), pmx_off);
   };
+  auto derive = [&](Row2 &d) {
+    d.l = shift_left(d.h, d.v);
+    d.r = shift_right(d.h, d.v);
+  };
   unsigned wlo = 0, whi = 0;
 
-  // A row is read shifted right as "hi" (form 0) and "mid" (1), shifted
-  // left as "mid" (0) and "lo" (1).
   auto step = [&](int y, bool even, const Row2 &lo, const Row2 &mid,
                   const Row2 &hi) {
     const float c = mid.v;
     unsigned m;
-    m = push_sign(0u, from_right<0>(hi.v) - c);  // 5 (1,1)
-    m = push_sign(m, c - from_left<1>(lo.v));    // 4 (-1,-1)
-    m = push_sign(m, hi.v - c);                  // 3 (0,1)
-    m = push_sign(m, c - lo.v);                  // 2 (0,-1)
-    m = push_sign(m, from_right<1>(mid.v) - c);  // 1 (1,0)
-    m = push_sign(m, c - from_left<0>(mid.v));   // 0 (-1,0)
+    m = push_sign(0u, hi.r - c);   // 5 (1,1)
+    m = push_sign(m, c - lo.l);    // 4 (-1,-1)
+    m = push_sign(m, hi.v - c);    // 3 (0,1)
+    m = push_sign(m, c - lo.v);    // 2 (0,-1)
+    m = push_sign(m, mid.r - c);   // 1 (1,0)
+    m = push_sign(m, c - mid.l);   // 0 (-1,0)
     if (wave_ballot(special_centre(c))) {
-      const float nb[6] = {nb_left(mid.v), nb_right(mid.v), lo.v, hi.v,
-                           nb_left(lo.v), nb_right(hi.v)};
+      const float nb[6] = {mid.l, mid.r, lo.v, hi.v, lo.l, hi.r};
       const unsigned ex = mask2(c, nb) ^ kPos2;
       m = special_centre(c) ? ex : m;
       nan_seen |= y < y1 && out_lane && (c != c);
@@ -686,8 +743,8 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
       reclass += (unsigned)__popcll(dm);
     }
     const int q = y - y0;
-    stc[q * 64 + lane] = (uint8_t)out;
-    if (WM && store_masks) stm[q * 64 + lane] = (uint8_t)m;
+    stc[lane * kCodeStride2 + q] = (uint8_t)out;
+    if (WM && store_masks) stm[lane * kMaskStride2 + q] = (uint8_t)m;
     wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
     whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
   };
@@ -697,10 +754,13 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   Row2 W[U];
 #pragma unroll
   for (int s = 0; s < U - 1; s++) load(y0 - 1 + s, (s & 1) != 0, W[s]);
+  derive(W[0]);
+  derive(W[1]);
   for (int yb = y0; yb < y1; yb += U) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int y = yb + u;
+      derive(W[(u + 2) % U]);  // row y+1
       load(y + U - 2, !(u & 1), W[(u + U - 1) % U]);
       step(y, !(u & 1), W[u % U], W[(u + 1) % U], W[(u + 2) % U]);
     }
@@ -710,22 +770,43 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const uint64_t wbits = (((uint64_t)whi << 32) | wlo) & out_lanes;
   if (lane < nrows) g.bits[(int64_t)(y0 + lane) * g.rowwords + tx] = wbits;
   if (!out_lane) return;
+  constexpr int NQ = kYChunk2;
+  constexpr int ND = (NQ + 3) / 4;
+  uint32_t cw[ND];
+  auto read_stage = [&](const uint8_t *base, int stride) {
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(base + lane * stride);
+#pragma unroll
+    for (int k = 0; k < ND; k++) cw[k] = sp[k];
+  };
+  auto staged = [&](int q) { return (cw[q >> 2] >> (8 * (q & 3))) & 0xFFu; };
+  read_stage(stc, kCodeStride2);
   if (g.write_codes) {
     const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
     uint8_t *cp = a.codes + (int64_t)y0 * g.sy;
-    for (int q = 0; q < nrows; q++, cp += g.sy) {
-      const unsigned b = stc[q * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < NQ; q++, cp += g.sy) {
+      if (q >= nrows) break;
+      const unsigned b = staged(q);
       // clean old vertices (even rows) keep their code
       if (!(keep_clean && !(q & 1)) || b != kKeep) st_u8(rsrc(cp), xoffc, b);
     }
   }
   if (g.lcodes) {
     uint8_t *lp = g.lcodes + (int64_t)y0 * mx;
-    for (int q = 0; q < nrows; q++, lp += mx) st_u8(rsrc(lp), (uint32_t)x, stc[q * 64 + lane]);
+#pragma unroll
+    for (int q = 0; q < NQ; q++, lp += mx) {
+      if (q >= nrows) break;
+      st_u8(rsrc(lp), (uint32_t)x, staged(q));
+    }
   }
   if (WM && store_masks) {
+    read_stage(stm, kMaskStride2);
     char *mp = reinterpret_cast<char *>(g.masks) + (int64_t)y0 * mx;
-    for (int q = 0; q < nrows; q++, mp += mx) st_u8(rsrc(mp), (uint32_t)x, stm[q * 64 + lane]);
+#pragma unroll
+    for (int q = 0; q < NQ; q++, mp += mx) {
+      if (q >= nrows) break;
+      st_u8(rsrc(mp), (uint32_t)x, staged(q));
+    }
   }
 }
 
@@ -749,8 +830,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   static_assert(ZC % kUnroll3 == 0, "tile depth must be a multiple of the unroll");
   static_assert(ZC * R <= 64, "one critical word per lane");
   __shared__ __attribute__((aligned(16))) uint8_t slut[kLut3Size];
-  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][ZC * R * 64];
-  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? ZC * R * 64 : 2];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * kCodeStride3];
+  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? 64 * kMaskStride3 : 2];
   __shared__ unsigned s_reclass[kMaxFused];
 
   // the wave index is the same in every lane: keep tile arithmetic scalar
@@ -785,8 +866,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   }
   if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
   __syncthreads();
-  if ((RP || FAR) && tid < a.nl)
-    a.reclass_part[(int64_t)blockIdx.x * kMaxFused + tid] = s_reclass[tid];
+  if ((RP || FAR) && tid < a.nl && s_reclass[tid])
+    atomicAdd(&a.reclass_acc[tid], s_reclass[tid]);
 }
 
 template <bool RP, bool WM, bool FAR>
@@ -796,8 +877,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
   constexpr int YC = kYChunk2;
   static_assert(YC % kUnroll2 == 0 && YC <= 64, "tile depth");
   __shared__ uint8_t slut[kLut2Size];
-  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][YC * 64];
-  __shared__ uint8_t smask[WM ? NW : 1][WM ? YC * 64 : 4];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * kCodeStride2];
+  __shared__ __attribute__((aligned(16))) uint8_t smask[WM ? NW : 1][WM ? 64 * kMaskStride2 : 4];
   __shared__ unsigned s_reclass[kMaxFused];
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -827,8 +908,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
   }
   if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
   __syncthreads();
-  if ((RP || FAR) && tid < a.nl)
-    a.reclass_part[(int64_t)blockIdx.x * kMaxFused + tid] = s_reclass[tid];
+  if ((RP || FAR) && tid < a.nl && s_reclass[tid])
+    atomicAdd(&a.reclass_acc[tid], s_reclass[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -893,9 +974,8 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   constexpr int CW = T * WPT;
   constexpr int NWV = T / 64;
   __shared__ int64_t s_red[NWV];
-  __shared__ unsigned s_ured[NWV];
   __shared__ int s_wtot[NWV];
-  __shared__ uint16_t s_ent[T * kTileOut];
+  __shared__ uint16_t s_ent[T * kTileCols];
   __shared__ uint32_t s_row0[T];
   const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -933,12 +1013,11 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   const int64_t lprefix = block_sum(lpart, s_red);
   // lists of earlier launches end at level_base[first slot of this launch]
   const int64_t base = a.level_base[a.lv[0].slot];
-  if (lchunk == 0 && L.reclass_out) {
-    unsigned r = 0;
-    for (int i = tid; i < a.reclass_blocks; i += T)
-      r += a.reclass_part[(int64_t)i * kMaxFused + li];
-    r = block_sum(r, s_ured);
-    if (tid == 0) *L.reclass_out = r;
+  if (lchunk == 0 && tid == 0) {
+    // the counter starts at zero for the next launch on this stream
+    const unsigned r = a.reclass_acc[li];
+    a.reclass_acc[li] = 0u;
+    if (L.reclass_out) *L.reclass_out = r;
   }
 
   const int64_t rowstep = L.s * a.nx;
@@ -964,12 +1043,12 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
       tot += s_wtot[i];
     }
     if (word) {
-      // word gw covers columns 62*xw + (bit - 1) of level row r
+      // word gw covers columns 64*xw + bit of level row r
       const uint32_t r = (uint32_t)gw / (uint32_t)L.rowwords;
       const uint32_t xw = (uint32_t)gw - r * (uint32_t)L.rowwords;
       const uint32_t zz = r / (uint32_t)L.my, yy = r - zz * (uint32_t)L.my;
       s_row0[tid] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
-                               L.s * ((int64_t)xw * kTileOut - 1));
+                               L.s * (int64_t)xw * kTileCols);
       int o = woff + incl - cnt;
       while (word) {
         s_ent[o++] = (uint16_t)(tid << 6 | __builtin_ctzll(word));
@@ -1012,29 +1091,19 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   }
 }
 
-// Persistent grid size: resident blocks per CU x CUs, at most 8 per CU.
-template <typename K>
-int persistent_blocks(K kernel, int threads) {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-          hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) !=
-          hipSuccess)
-    return 256;
-  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
-  return cus * per_cu;
-}
+// Grid of a classification launch: every wave takes kTileRounds tiles (the
+// kernels stride over the tiles by the grid's wave count).  Short blocks
+// let the dispatcher balance tiles of unequal cost (boundary tiles, the
+// re-classification branch) over the CUs better than a fixed persistent
+// share per block does.
+constexpr int kTileRounds = 2;
 
-template <typename K>
-hipError_t launch_persistent(K kernel, const ClassifyArgs &a, hipStream_t st,
-                             int *grid_out) {
+template <auto Kernel>
+hipError_t launch_tiles(const ClassifyArgs &a, hipStream_t st) {
   const int threads = 64 * kWavesPerBlock;
-  static const int nb = persistent_blocks(kernel, threads);
-  const int want = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int g = want < nb ? want : nb;
-  *grid_out = g;
-  hipLaunchKernelGGL(kernel, dim3((unsigned)g), dim3(threads), 0, st, a);
+  const int64_t per_block = (int64_t)kWavesPerBlock * kTileRounds;
+  const int g = (int)((a.ntiles + per_block - 1) / per_block);
+  hipLaunchKernelGGL(Kernel, dim3((unsigned)(g > 0 ? g : 1)), dim3(threads), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1050,17 +1119,8 @@ int tile_depth(int64_t columns, int n, int cap, int step) {
 
 }  // namespace
 
-int classify_max_blocks() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-          hipSuccess)
-    cus = 256;
-  return cus * 8;
-}
-
 void plan_level3(LevelDesc &l) {
-  l.ntx = (l.mx + kTileOut - 1) / kTileOut;
+  l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = (l.my + kTile3Y - 1) / kTile3Y;
   l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, kZChunk3, kUnroll3);
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
@@ -1069,7 +1129,7 @@ void plan_level3(LevelDesc &l) {
 }
 
 void plan_level2(LevelDesc &l) {
-  l.ntx = (l.mx + kTileOut - 1) / kTileOut;
+  l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = 1;
   l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2);
   l.ntiles = l.ntx * ((l.my + l.zchunk - 1) / l.zchunk);
@@ -1078,29 +1138,29 @@ void plan_level2(LevelDesc &l) {
 }
 
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
-                           bool write_masks, hipStream_t st, int *grid_out) {
+                           bool write_masks, hipStream_t st) {
   // fused launches compute the previous level's masks from the field
   const bool fused = a.nl > 1;
   if (dim == 3) {
     if (fused)
-      return launch_persistent(classify3d_kernel<false, true, true>, a, st, grid_out);
+      return launch_tiles<classify3d_kernel<false, true, true>>(a, st);
     if (read_prev && write_masks)
-      return launch_persistent(classify3d_kernel<true, true, false>, a, st, grid_out);
+      return launch_tiles<classify3d_kernel<true, true, false>>(a, st);
     if (read_prev)
-      return launch_persistent(classify3d_kernel<true, false, false>, a, st, grid_out);
+      return launch_tiles<classify3d_kernel<true, false, false>>(a, st);
     if (write_masks)
-      return launch_persistent(classify3d_kernel<false, true, false>, a, st, grid_out);
-    return launch_persistent(classify3d_kernel<false, false, false>, a, st, grid_out);
+      return launch_tiles<classify3d_kernel<false, true, false>>(a, st);
+    return launch_tiles<classify3d_kernel<false, false, false>>(a, st);
   }
   if (fused)
-    return launch_persistent(classify2d_kernel<false, true, true>, a, st, grid_out);
+    return launch_tiles<classify2d_kernel<false, true, true>>(a, st);
   if (read_prev && write_masks)
-    return launch_persistent(classify2d_kernel<true, true, false>, a, st, grid_out);
+    return launch_tiles<classify2d_kernel<true, true, false>>(a, st);
   if (read_prev)
-    return launch_persistent(classify2d_kernel<true, false, false>, a, st, grid_out);
+    return launch_tiles<classify2d_kernel<true, false, false>>(a, st);
   if (write_masks)
-    return launch_persistent(classify2d_kernel<false, true, false>, a, st, grid_out);
-  return launch_persistent(classify2d_kernel<false, false, false>, a, st, grid_out);
+    return launch_tiles<classify2d_kernel<false, true, false>>(a, st);
+  return launch_tiles<classify2d_kernel<false, false, false>>(a, st);
 }
 
 hipError_t launch_compact(const CompactArgs &a, bool fused, hipStream_t st) {

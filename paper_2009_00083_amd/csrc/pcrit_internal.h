@@ -44,14 +44,13 @@ constexpr int kCompactThreads = 256;
 constexpr int kCompactWordsPerThread = 4;
 constexpr int kChunkWords = kCompactThreads * kCompactWordsPerThread;
 
-// Tiles of the classification kernels.  A wave holds 64 consecutive x (one
-// sample per lane) and classifies the kTileOut columns of lanes 1..62;
-// lanes 0 and 63 only supply the x-1 / x+1 neighbours of lanes 1 and 62.
-// The tile spans kTile3Y rows (3D) or one row (2D) and is marched along the
-// slowest axis; the waves of a block only share the link-pattern table.
-// A critical-bitmask word covers the kTileOut columns of one tile row: bit
-// L (1..62) is column word*kTileOut + L - 1.
-constexpr int kTileOut = 62;
+// Tiles of the classification kernels.  A wave holds 64 consecutive
+// columns (one per lane) of kTile3Y rows (3D) or one row (2D), plus the
+// columns left and right of the tile from a halo load, and marches them along
+// the slowest axis; the waves of a block only share the link-pattern table.
+// A critical-bitmask word covers the kTileCols columns of one tile row: bit
+// L is column word*kTileCols + L.
+constexpr int kTileCols = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kTile3Y = 2;    // rows per 3D wave tile
 constexpr int kZChunk3 = 24;  // planes per 3D wave tile
@@ -103,7 +102,7 @@ struct ClassifyArgs {
   int nl;               // levels in this launch (1, or several when fused)
   int ntiles;           // wave tiles of all levels
   LevelDesc lv[kMaxFused];
-  unsigned *reclass_part;  // per block and level: re-classified old vertices
+  unsigned *reclass_acc;   // per level: re-classified old vertices (added to)
   unsigned *nan_flag;      // set to gen if a level sample is NaN
   unsigned gen;
 };
@@ -117,7 +116,7 @@ struct CompactLevel {
   int slot;             // list of this level: level_base[slot] onwards
   int chunk_begin;      // first chunk of this level (chunks in list order)
   const uint8_t *lcodes;  // dense level codes for crit_codes, or null
-  unsigned *reclass_out;  // sum of reclass_part column `index`, or null
+  unsigned *reclass_out;  // receives reclass_acc[level index], or null
 };
 
 struct CompactArgs {
@@ -134,8 +133,7 @@ struct CompactArgs {
   unsigned *nan_flag;
   unsigned gen;
   int *counts;          // per-chunk critical counts
-  const unsigned *reclass_part;
-  int reclass_blocks;   // rows of reclass_part (blocks of the classify launch)
+  unsigned *reclass_acc;  // read into reclass_out, then cleared
 };
 
 // Fill the launch geometry of a level (tile depth, tile counts).
@@ -155,12 +153,9 @@ inline void fast_divisor(uint32_t d, uint32_t *mul, int *shift) {
 constexpr int kFusedWordsPerThread = 1;
 constexpr int kFusedChunkWords = kCompactThreads * kFusedWordsPerThread;
 
-// Launchers; *grid_out receives the number of blocks of the classification.
+// Launchers.
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
-                           bool write_masks, hipStream_t st, int *grid_out);
+                           bool write_masks, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, bool fused, hipStream_t st);
-
-// Upper bound of the blocks of a classification launch.
-int classify_max_blocks();
 
 }  // namespace pcrit
