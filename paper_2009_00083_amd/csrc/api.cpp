@@ -160,7 +160,9 @@ int64_t level_vertices(const Geom &g) { return g.mx * g.my * g.mz; }
 void launch_needs(const Step *steps, int n, bool with_codes, int64_t *words,
                   int64_t *chunks, int64_t *lbytes) {
   const bool fused = n > 1;
-  const int64_t cw = fused ? kFusedChunkWords : kChunkWords;
+  int64_t total = 0;
+  for (int l = 0; l < n; l++) total += steps[l].g.words;
+  const int64_t cw = small_chunks(total) ? kSmallChunkWords : kChunkWords;
   *words = *chunks = *lbytes = 0;
   for (int l = 0; l < n; l++) {
     *words += steps[l].g.words;
@@ -181,7 +183,10 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   unsigned gen) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
-  const int64_t cw = fused ? kFusedChunkWords : kChunkWords;
+  int64_t total_words = 0;
+  for (int l = 0; l < n; l++) total_words += steps[l].g.words;
+  const bool small = small_chunks(total_words);
+  const int64_t cw = small ? kSmallChunkWords : kChunkWords;
   ClassifyArgs a{};
   a.f = field;
   a.codes = codes;
@@ -207,7 +212,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     d.mz = (int)g.mz;
     d.rowwords = (int)g.rowwords;
     if (dim == 3)
-      plan_level3(d);
+      plan_level3(d, fused || steps[0].mask_write >= 0);
     else
       plan_level2(d);
     d.tile_begin = tiles;
@@ -262,7 +267,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   b.counts = c->counts;
   b.reclass_acc = c->reclass_acc;
   record_kernel(c, 1, tlevel, 0, st);
-  if (launch_compact(b, fused, st) != hipSuccess) return PCRIT_E_HIP;
+  if (launch_compact(b, small, st) != hipSuccess) return PCRIT_E_HIP;
   record_kernel(c, 1, tlevel, 1, st);
   return PCRIT_OK;
 }

@@ -130,9 +130,9 @@ constexpr uint8_t kKeep = 0xFF;  // staging: no code to write (never a code)
 // stride in dwords is odd, which keeps the per-row byte writes of the 64
 // lanes in distinct banks.
 constexpr int stage_dwords(int bytes) { return ((bytes + 3) / 4) | 1; }
-constexpr int kRows3 = kZChunk3 * kTile3Y;                   // staged rows (3D)
-constexpr int kCodeStride3 = 4 * stage_dwords(kRows3);       // bytes per lane
-constexpr int kMaskStride3 = 2 * stage_dwords(2 * kRows3);   // u16 per lane
+// 3D, for tiles of at most ZC planes: bytes of codes / u16 of masks per lane
+constexpr int code_stride3(int zc) { return 4 * stage_dwords(zc * kTile3Y); }
+constexpr int mask_stride3(int zc) { return 2 * stage_dwords(2 * zc * kTile3Y); }
 constexpr int kCodeStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
 constexpr int kMaskStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
 constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
@@ -309,7 +309,7 @@ __device__ __forceinline__ int tile_class3(const LevelDesc &g, int t) {
   return (y_in && z_in) ? (x_in ? 1 : 2) : 0;
 }
 
-template <int R, bool RP, bool WM, bool FAR, int MODE>
+template <int R, int ZC, bool RP, bool WM, bool FAR, int MODE>
 __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
                                        const LevelDesc &g, int t, int lane,
                                        const uint8_t *slut, uint8_t *stc,
@@ -498,8 +498,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
           reclass += (unsigned)__popcll(dm);
         }
         const int q = qb + j;
-        stc[lane * kCodeStride3 + q] = (uint8_t)out;
-        if (WM && store_masks) stm[lane * kMaskStride3 + q] = (uint16_t)mr[j];
+        stc[lane * code_stride3(ZC) + q] = (uint8_t)out;
+        if (WM && store_masks) stm[lane * mask_stride3(ZC) + q] = (uint16_t)mr[j];
         wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
         whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
       }
@@ -556,11 +556,10 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   const int nyl = min(R, my - y0);
   const int nzl = z1 - z0;
   // this lane's staged codes, four rows per dword, read at once
-  constexpr int NQ = kZChunk3 * R;
-  static_assert(NQ == kRows3, "staging geometry");
+  constexpr int NQ = ZC * R;
   uint32_t cw[NQ / 4];
   {
-    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stc + lane * kCodeStride3);
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stc + lane * code_stride3(ZC));
 #pragma unroll
     for (int k = 0; k < NQ / 4; k++) cw[k] = sp[k];
   }
@@ -570,7 +569,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
     uint8_t *cp = a.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy;
 #pragma unroll
-    for (int zz = 0; zz < kZChunk3; zz++, cp += g.sz) {
+    for (int zz = 0; zz < ZC; zz++, cp += g.sz) {
       if (zz >= nzl) break;
 #pragma unroll
       for (int j = 0; j < R; j++) {
@@ -586,7 +585,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     uint8_t *lp = g.lcodes + ((int64_t)z0 * my + y0) * mx;
     const int64_t lplane = (int64_t)my * mx;
 #pragma unroll
-    for (int zz = 0; zz < kZChunk3; zz++, lp += lplane) {
+    for (int zz = 0; zz < ZC; zz++, lp += lplane) {
       if (zz >= nzl) break;
 #pragma unroll
       for (int j = 0; j < R; j++) {
@@ -597,7 +596,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   }
   if (WM && store_masks) {
     // masks: two rows per dword, read in groups of NQ / 4 dwords
-    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stm + lane * kMaskStride3);
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stm + lane * mask_stride3(ZC));
     char *mp = reinterpret_cast<char *>(g.masks) + (((int64_t)z0 * my + y0) * mx) * 2;
     const int64_t mplane = (int64_t)my * mx * 2;
 #pragma unroll
@@ -605,8 +604,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
 #pragma unroll
       for (int k = 0; k < NQ / 4; k++) cw[k] = sp[h * (NQ / 4) + k];
 #pragma unroll
-      for (int zl = 0; zl < kZChunk3 / 2; zl++, mp += mplane) {
-        const int zz = h * (kZChunk3 / 2) + zl;
+      for (int zl = 0; zl < ZC / 2; zl++, mp += mplane) {
+        const int zz = h * (ZC / 2) + zl;
         if (zz >= nzl) break;
 #pragma unroll
         for (int j = 0; j < R; j++) {
@@ -826,12 +825,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
     ClassifyArgs a) {
   constexpr int NW = kWavesPerBlock;
   constexpr int R = kTile3Y;
-  constexpr int ZC = kZChunk3;
+  constexpr int ZC = zchunk_cap3(WM);
   static_assert(ZC % kUnroll3 == 0, "tile depth must be a multiple of the unroll");
   static_assert(ZC * R <= 64, "one critical word per lane");
+  static_assert(ZC % 2 == 0, "mask staging in two halves");
   __shared__ __attribute__((aligned(16))) uint8_t slut[kLut3Size];
-  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * kCodeStride3];
-  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? 64 * kMaskStride3 : 2];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * code_stride3(ZC)];
+  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? 64 * mask_stride3(ZC) : 2];
   __shared__ unsigned s_reclass[kMaxFused];
 
   // the wave index is the same in every lane: keep tile arithmetic scalar
@@ -854,13 +854,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
     const int tt = t - lv.tile_begin;
     const int cls = tile_class3<R>(lv, tt);
     if (cls == 1)
-      tile3d<R, RP, WM, FAR, 1>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+      tile3d<R, ZC, RP, WM, FAR, 1>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
                                 nan_seen, reclass);
     else if (cls == 2)
-      tile3d<R, RP, WM, FAR, 2>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+      tile3d<R, ZC, RP, WM, FAR, 2>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
                                 nan_seen, reclass);
     else
-      tile3d<R, RP, WM, FAR, 0>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
+      tile3d<R, ZC, RP, WM, FAR, 0>(a, lv, tt, lane, slut, scode[w], smask[WM ? w : 0],
                                 nan_seen, reclass);
     if ((RP || FAR) && lane == 0 && reclass) atomicAdd(&s_reclass[l], reclass);
   }
@@ -1092,7 +1092,8 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
 }
 
 // Grid of a classification launch: every wave takes kTileRounds tiles (the
-// kernels stride over the tiles by the grid's wave count).  Short blocks
+// kernels stride over the tiles by the grid's wave count), one in fused
+// launches of small levels, whose few tiles are latency bound.  Short blocks
 // let the dispatcher balance tiles of unequal cost (boundary tiles, the
 // re-classification branch) over the CUs better than a fixed persistent
 // share per block does.
@@ -1101,7 +1102,7 @@ constexpr int kTileRounds = 2;
 template <auto Kernel>
 hipError_t launch_tiles(const ClassifyArgs &a, hipStream_t st) {
   const int threads = 64 * kWavesPerBlock;
-  const int64_t per_block = (int64_t)kWavesPerBlock * kTileRounds;
+  const int64_t per_block = (int64_t)kWavesPerBlock * (a.nl > 1 ? 1 : kTileRounds);
   const int g = (int)((a.ntiles + per_block - 1) / per_block);
   hipLaunchKernelGGL(Kernel, dim3((unsigned)(g > 0 ? g : 1)), dim3(threads), 0, st, a);
   return hipGetLastError();
@@ -1119,10 +1120,10 @@ int tile_depth(int64_t columns, int n, int cap, int step) {
 
 }  // namespace
 
-void plan_level3(LevelDesc &l) {
+void plan_level3(LevelDesc &l, bool write_masks) {
   l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = (l.my + kTile3Y - 1) / kTile3Y;
-  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, kZChunk3, kUnroll3);
+  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, zchunk_cap3(write_masks), kUnroll3);
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor((uint32_t)l.nty, &l.nty_mul, &l.nty_shift);
@@ -1142,6 +1143,9 @@ hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
   // fused launches compute the previous level's masks from the field
   const bool fused = a.nl > 1;
   if (dim == 3) {
+    // the kernel's LDS staging holds tiles of at most zchunk_cap3 planes
+    for (int l = 0; l < a.nl; l++)
+      if (a.lv[l].zchunk > zchunk_cap3(fused || write_masks)) return hipErrorInvalidValue;
     if (fused)
       return launch_tiles<classify3d_kernel<false, true, true>>(a, st);
     if (read_prev && write_masks)
@@ -1163,10 +1167,10 @@ hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
   return launch_tiles<classify2d_kernel<false, false, false>>(a, st);
 }
 
-hipError_t launch_compact(const CompactArgs &a, bool fused, hipStream_t st) {
+hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st) {
   if (a.nchunks > 1) {
-    if (fused)
-      hipLaunchKernelGGL(count_kernel<kFusedWordsPerThread>, dim3((unsigned)a.nchunks),
+    if (small)
+      hipLaunchKernelGGL(count_kernel<kSmallWordsPerThread>, dim3((unsigned)a.nchunks),
                          dim3(kCompactThreads), 0, st, a);
     else
       hipLaunchKernelGGL(count_kernel<kCompactWordsPerThread>,
@@ -1174,8 +1178,8 @@ hipError_t launch_compact(const CompactArgs &a, bool fused, hipStream_t st) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (fused)
-    hipLaunchKernelGGL(expand_kernel<kFusedWordsPerThread>, dim3((unsigned)a.nchunks),
+  if (small)
+    hipLaunchKernelGGL(expand_kernel<kSmallWordsPerThread>, dim3((unsigned)a.nchunks),
                        dim3(kCompactThreads), 0, st, a);
   else
     hipLaunchKernelGGL(expand_kernel<kCompactWordsPerThread>,

@@ -54,6 +54,10 @@ constexpr int kTileCols = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kTile3Y = 2;    // rows per 3D wave tile
 constexpr int kZChunk3 = 24;  // planes per 3D wave tile
+// Launches that store masks stage twice as many bytes per vertex in LDS;
+// their tiles are shallower so that four blocks fit on a CU.
+constexpr int kZChunk3Masks = 12;
+constexpr int zchunk_cap3(bool write_masks) { return write_masks ? kZChunk3Masks : kZChunk3; }
 constexpr int kYChunk2 = 60;  // rows per 2D wave tile
 constexpr int kUnroll3 = 6;   // 3D march unroll (planes in registers)
 constexpr int kUnroll2 = 12;  // 2D march unroll (rows in registers)
@@ -137,7 +141,7 @@ struct CompactArgs {
 };
 
 // Fill the launch geometry of a level (tile depth, tile counts).
-void plan_level3(LevelDesc &l);
+void plan_level3(LevelDesc &l, bool write_masks);
 void plan_level2(LevelDesc &l);
 
 // Division by an invariant d in [1, 2^31): with l = ceil(log2 d),
@@ -149,13 +153,18 @@ inline void fast_divisor(uint32_t d, uint32_t *mul, int *shift) {
   *shift = 31 + l;
   *mul = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
 }
-// Chunks of kChunkWords words (single level) or kFusedChunkWords (fused).
-constexpr int kFusedWordsPerThread = 1;
-constexpr int kFusedChunkWords = kCompactThreads * kFusedWordsPerThread;
+// Compaction chunks: kChunkWords words, or kSmallChunkWords for launches of
+// at most kSmallLaunchWords words (fused levels, level 1), which would
+// otherwise have too few chunks to fill the GPU.  Every chunk sums the
+// counts of all chunks before it, so big launches take the big chunks.
+constexpr int kSmallWordsPerThread = 1;
+constexpr int kSmallChunkWords = kCompactThreads * kSmallWordsPerThread;
+constexpr int64_t kSmallLaunchWords = int64_t(1) << 19;
+inline bool small_chunks(int64_t launch_words) { return launch_words <= kSmallLaunchWords; }
 
 // Launchers.
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
                            bool write_masks, hipStream_t st);
-hipError_t launch_compact(const CompactArgs &a, bool fused, hipStream_t st);
+hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st);
 
 }  // namespace pcrit
