@@ -240,6 +240,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     q.chunk_begin = (int)chunks;
     q.lcodes = d.lcodes;
     q.reclass_out = sp.reclass_out;
+    q.linear = g.s == 1 && g.mx == g.rowwords * kTileCols;
     woff += g.words;
     if (d.lcodes) loff += level_vertices(g);
     chunks += (g.words + cw - 1) / cw;

@@ -316,8 +316,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
                                        uint16_t *stm, bool &nan_seen,
                                        unsigned &reclass) {
   constexpr int NR = R + 2;
-  constexpr int U = kUnroll3;  // ring of planes z-1 .. z+4
-  static_assert(U == 6 && R % 2 == 0, "plane ring and row parity");
+  constexpr int U = kUnroll3;  // ring of planes z-1 .. z+U-2
+  static_assert(U >= 4 && U % 2 == 0 && R % 2 == 0, "plane ring and row parity");
   const int mx = g.mx, my = g.my, mz = g.mz;
   const TilePos tp = tile_pos(g, t);
   const int tx = tp.tx, ty = tp.ty, zc = tp.zc;
@@ -507,8 +507,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     rows(std::integral_constant<bool, MODE != 0>{});
   };
 
-  // Prologue: planes z0-1 .. z0+3 in flight; plane z sits in slot
-  // (z - z0 + 1) % 6, and step z loads plane z+4 into the slot of z-2.
+  // Prologue: planes z0-1 .. z0+U-3 in flight; plane z sits in slot
+  // (z - z0 + 1) % U, and step z loads plane z+U-2 into the slot of z-2.
   Plane3<R> W[U];
 #pragma unroll
   for (int s = 0; s < U - 1; s++) {
@@ -517,13 +517,13 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   }
   derive(W[0]);
   derive(W[1]);
-  // running pointers to plane zn = z+4, clamped to plane z1 (the last one
+  // running pointers to plane zn = z+U-2, clamped to plane z1 (the last one
   // the tile reads: the plane above its last classified plane) so that the
   // steps past the tile re-read a plane in cache instead of the next tile's
   const int zlast = min(z1, mz - 1);
-  const char *pn = plane_at(min(z0 + 4, zlast));
-  const char *pmn = pmplane_at(min(z0 + 4, zlast));
-  int zn = z0 + 4;
+  const char *pn = plane_at(min(z0 + U - 2, zlast));
+  const char *pmn = pmplane_at(min(z0 + U - 2, zlast));
+  int zn = z0 + U - 2;
   // zchunk is a multiple of U; a short last tile runs up to U-1 extra steps
   // whose staged rows are never written out.
   for (int zb = z0; zb < z1; zb += U) {
@@ -531,7 +531,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     for (int u = 0; u < U; u++) {
       const int z = zb + u;
       derive(W[(u + 2) % U]);  // plane z+1
-      load(pn, pmn, !(u & 1), W[(u + 5) % U]);
+      load(pn, pmn, !(u & 1), W[(u + U - 1) % U]);
       if (zn < zlast) {
         pn += szb;
         if (u & 1) pmn += pmplane;  // plane zn+1 is even
@@ -962,12 +962,28 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(CompactArgs a) {
   if (tid == 0) a.counts[chunk] = tot;
 }
 
+// Inclusive prefix sum over the lanes of a wave: shifts within the 16-lane
+// DPP rows, then the row broadcasts of lanes 15 and 31.  Lanes without a
+// source add the `old` operand, 0.
+__device__ __forceinline__ int wave_inclusive_sum(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
 // expand_kernel: the chunk's words are loaded at once (WPT per thread) and
 // processed in WPT rounds of one word per thread.  In a round every thread
 // expands its word into LDS at its position (block scan of the popcounts) as
-// 16-bit entries (word << 6 | bit), then the block writes the round's
-// entries to the list with coalesced stores.  Entries are in index order
-// because words are in index order and bits are expanded low to high.
+// 16-bit entries (word << 6 | bit), the two 32-bit halves side by side, then
+// the block writes the round's entries to the list with coalesced stores.
+// Entries are in index order because words are in index order and bits are
+// expanded low to high.  On a linear level (full resolution, rows a whole
+// number of words) the index of an entry is 64 * (first word of the round)
+// + entry; otherwise it comes from the word's row start.
 template <int WPT>
 __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) {
   constexpr int T = kCompactThreads;
@@ -975,7 +991,7 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   constexpr int NWV = T / 64;
   __shared__ int64_t s_red[NWV];
   __shared__ int s_wtot[NWV];
-  __shared__ uint16_t s_ent[T * kTileCols];
+  __shared__ uint16_t s_ent[T * 64];
   __shared__ uint32_t s_row0[T];
   const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1020,21 +1036,27 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
     if (L.reclass_out) *L.reclass_out = r;
   }
 
+  const bool linear = L.linear && !a.crit_codes;
   const int64_t rowstep = L.s * a.nx;
   const uint32_t s = (uint32_t)L.s;
   int64_t done = 0;  // entries of this chunk written so far
 #pragma unroll
   for (int k = 0; k < WPT; k++) {
-    const int64_t gw = wfirst + (int64_t)k * T + tid;
-    uint64_t word = wd[k];
-    const int cnt = __popcll(word);
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
+    const int64_t gw0 = wfirst + (int64_t)k * T;  // first word of the round
+    uint32_t lo = (uint32_t)wd[k], hi = (uint32_t)(wd[k] >> 32);
+    const int plo = __popc(lo);
+    const int cnt = plo + __popc(hi);
+    const int incl = wave_inclusive_sum(cnt);
     if (lane == 63) s_wtot[w] = incl;
+    if (!linear && (lo | hi)) {
+      // word gw covers columns 64*xw + bit of level row r
+      const uint32_t gw = (uint32_t)(gw0 + tid);
+      const uint32_t r = gw / (uint32_t)L.rowwords;
+      const uint32_t xw = gw - r * (uint32_t)L.rowwords;
+      const uint32_t zz = r / (uint32_t)L.my, yy = r - zz * (uint32_t)L.my;
+      s_row0[tid] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
+                               L.s * (int64_t)xw * kTileCols);
+    }
     __syncthreads();
     int woff = 0, tot = 0;
 #pragma unroll
@@ -1042,37 +1064,59 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
       woff += i < w ? s_wtot[i] : 0;
       tot += s_wtot[i];
     }
-    if (word) {
-      // word gw covers columns 64*xw + bit of level row r
-      const uint32_t r = (uint32_t)gw / (uint32_t)L.rowwords;
-      const uint32_t xw = (uint32_t)gw - r * (uint32_t)L.rowwords;
-      const uint32_t zz = r / (uint32_t)L.my, yy = r - zz * (uint32_t)L.my;
-      s_row0[tid] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
-                               L.s * (int64_t)xw * kTileCols);
-      int o = woff + incl - cnt;
-      while (word) {
-        s_ent[o++] = (uint16_t)(tid << 6 | __builtin_ctzll(word));
-        word &= word - 1;
+    {
+      // low half into [o, o + plo), high half into [o + plo, o + cnt)
+      const unsigned e0 = (unsigned)tid << 6;
+      int o = woff + incl - cnt, oh = o + plo;
+      while (lo | hi) {
+        if (lo) {
+          s_ent[o++] = (uint16_t)(e0 | (unsigned)__builtin_ctz(lo));
+          lo &= lo - 1u;
+        }
+        if (hi) {
+          s_ent[oh++] = (uint16_t)(e0 | 32u | (unsigned)__builtin_ctz(hi));
+          hi &= hi - 1u;
+        }
       }
     }
     __syncthreads();
     const int64_t out0 = base + prefix + done;
-    for (int e = tid; e < tot; e += T) {
-      const int64_t pos = out0 + e;
-      if (pos < a.cap) {
+    // entries of this round that fit the capacity
+    const int lim = (int)max((int64_t)0, min((int64_t)tot, a.cap - out0));
+    uint32_t *dst = a.crit + out0;
+    if (linear) {
+      const uint32_t ibase = (uint32_t)(gw0 * 64);
+      constexpr int UW = 4;
+      for (int e0 = 0; e0 < lim; e0 += UW * T) {
+        uint32_t v[UW];
+#pragma unroll
+        for (int u = 0; u < UW; u++) {
+          const int e = e0 + u * T + tid;
+          v[u] = e < lim ? (uint32_t)s_ent[e] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < UW; u++) {
+          const int e = e0 + u * T + tid;
+          if (e < lim) dst[e] = ibase + v[u];
+        }
+      }
+    } else {
+      for (int e = tid; e < lim; e += T) {
         const unsigned ent = s_ent[e];
         const uint32_t idx = s_row0[ent >> 6] + s * (ent & 63u);
-        a.crit[pos] = idx;
+        dst[e] = idx;
         if (a.crit_codes) {
+          uint8_t code;
           if (L.lcodes) {
             // dense level index from the full-resolution one
             const uint32_t xf = idx % (uint32_t)a.nx, rest = idx / (uint32_t)a.nx;
             const uint32_t yf = rest % (uint32_t)a.ny, zf = rest / (uint32_t)a.ny;
             const int64_t lix = ((int64_t)(zf / s) * L.my + yf / s) * L.mx + xf / s;
-            a.crit_codes[pos] = L.lcodes[lix];
+            code = L.lcodes[lix];
           } else {
-            a.crit_codes[pos] = a.codes[idx];
+            code = a.codes[idx];
           }
+          a.crit_codes[out0 + e] = code;
         }
       }
     }

@@ -59,7 +59,7 @@ constexpr int kZChunk3 = 24;  // planes per 3D wave tile
 constexpr int kZChunk3Masks = 12;
 constexpr int zchunk_cap3(bool write_masks) { return write_masks ? kZChunk3Masks : kZChunk3; }
 constexpr int kYChunk2 = 60;  // rows per 2D wave tile
-constexpr int kUnroll3 = 6;   // 3D march unroll (planes in registers)
+constexpr int kUnroll3 = 4;   // 3D march unroll (ring of planes in registers)
 constexpr int kUnroll2 = 12;  // 2D march unroll (rows in registers)
 
 // Polarity bits of the offsets with a larger linear index (first non-zero
@@ -121,6 +121,7 @@ struct CompactLevel {
   int chunk_begin;      // first chunk of this level (chunks in list order)
   const uint8_t *lcodes;  // dense level codes for crit_codes, or null
   unsigned *reclass_out;  // receives reclass_acc[level index], or null
+  bool linear;          // full resolution, rows of whole words: index = 64 * word + bit
 };
 
 struct CompactArgs {
