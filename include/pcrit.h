@@ -144,7 +144,8 @@ typedef void (*pcrit_level_cb)(int level, int64_t count, void *user);
  * critical status, which is exact because the code is a function of the
  * mask and the absent set only.
  *   codes         device, nx*ny*nz bytes; ends holding the level-0 code of
- *                 every vertex
+ *                 every vertex (stored by the level-0 pass; coarser levels
+ *                 store theirs there only when crit_codes is set)
  *   crit          device; the ascending critical list of each level,
  *                 concatenated coarse to fine; crit_capacity entries
  *                 (the sum of the level sizes is always enough)

@@ -180,7 +180,7 @@ void launch_needs(const Step *steps, int n, bool with_codes, int64_t *words,
 int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   const Step *steps, int n, uint8_t *codes, uint32_t *crit,
                   uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
-                  unsigned gen) {
+                  unsigned gen, bool final_group) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -225,8 +225,10 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
       d.pmy = (int)sp.prev->my;
     }
     if (sp.mask_write >= 0) d.masks = c->masks[sp.mask_write];
-    d.write_codes = !fused || last;
-    d.keep_clean = !fused && sp.dirty;
+    // full-resolution codes: the last level of the call writes every code
+    // (a vertex's code at its finest level); earlier levels only when their
+    // lists carry codes
+    d.write_codes = (!fused || last) && (final_group || crit_codes != nullptr);
     d.dirty = sp.dirty;
 
     CompactLevel &q = b.lv[l];
@@ -422,7 +424,7 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
   st = enqueue_group(c, s, field, &step, 1, codes, crit, crit_codes,
-                     crit_capacity, crit_count_dev, gen);
+                     crit_capacity, crit_count_dev, gen, true);
   if (st) return st;
   if (!crit_count_host) return PCRIT_OK;
   if (read_status(c, s)) return PCRIT_E_HIP;
@@ -519,7 +521,7 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
     st = enqueue_group(c, s, field, &steps[i], n, codes, crit, crit_codes,
-                       crit_capacity, nullptr, gen);
+                       crit_capacity, nullptr, gen, i + n > kmax);
     if (st) return st;
     if (timed && hipEventRecord(c->ev_level[i + n - 1], s) != hipSuccess)
       return PCRIT_E_HIP;

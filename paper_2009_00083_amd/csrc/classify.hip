@@ -123,7 +123,6 @@ constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 //   the same L2.  A launch may cover several small levels (the progressive
 //   driver fuses the latency-bound coarse levels); a wave then looks up the
 //   level of its tile in the launch's level table.
-constexpr uint8_t kKeep = 0xFF;  // staging: no code to write (never a code)
 
 // LDS staging of a wave's tile, lane-major: lane l's staged rows are
 // contiguous at l * stride, so the flush reads four rows per dword.  The
@@ -330,7 +329,6 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   const uint64_t old_lanes = wave_ballot(out_lane && !(x & 1));
   const bool x_inner = x0 > 0 && x0 + kTileCols < mx;
   const bool dirty_test = (RP || FAR) && g.dirty;
-  const bool keep_clean = g.keep_clean;
   const bool store_masks = WM && g.masks != nullptr;
   const unsigned xA = absent_x3(x, mx);
   const int exc = coarse_last(mx), eyc = coarse_last(my), ezc = coarse_last(mz);
@@ -494,7 +492,6 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
           }
           const uint64_t old = (zlive && y < my) ? old_lanes : 0ull;
           const uint64_t dm = wave_ballot(d) & old;
-          if (keep_clean) out = lane_bit(old & ~dm) ? (unsigned)kKeep : out;
           reclass += (unsigned)__popcll(dm);
         }
         const int q = qb + j;
@@ -574,10 +571,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
 #pragma unroll
       for (int j = 0; j < R; j++) {
         if (j >= nyl) break;
-        const unsigned b = staged(zz * R + j);
-        // clean old vertices (even plane, even row) keep their code
-        if (!(keep_clean && !(zz & 1) && !(j & 1)) || b != kKeep)
-          st_u8(rsrc(cp + (int64_t)j * g.sy), xoffc, b);
+        st_u8(rsrc(cp + (int64_t)j * g.sy), xoffc, staged(zz * R + j));
       }
     }
   }
@@ -657,7 +651,6 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const uint64_t old_lanes = wave_ballot(out_lane && !(x & 1));
   const bool x_inner = x0 > 0 && x0 + kTileCols < mx;
   const bool dirty_test = (RP || FAR) && g.dirty;
-  const bool keep_clean = g.keep_clean;
   const bool store_masks = WM && g.masks != nullptr;
   const unsigned xA = absent_x2(x, mx);
   const int exc = coarse_last(mx), eyc = coarse_last(my);
@@ -738,7 +731,6 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
       uint64_t dm = wave_ballot(d);
       const uint64_t old = y < y1 ? old_lanes : 0ull;
       dm &= old;
-      if (keep_clean) out = lane_bit(old & ~dm) ? (unsigned)kKeep : out;
       reclass += (unsigned)__popcll(dm);
     }
     const int q = y - y0;
@@ -785,9 +777,7 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
 #pragma unroll
     for (int q = 0; q < NQ; q++, cp += g.sy) {
       if (q >= nrows) break;
-      const unsigned b = staged(q);
-      // clean old vertices (even rows) keep their code
-      if (!(keep_clean && !(q & 1)) || b != kKeep) st_u8(rsrc(cp), xoffc, b);
+      st_u8(rsrc(cp), xoffc, staged(q));
     }
   }
   if (g.lcodes) {

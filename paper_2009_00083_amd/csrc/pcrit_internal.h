@@ -93,7 +93,6 @@ struct LevelDesc {
   int pmx, pmy;           // previous level sizes along x and y
   void *masks;            // this level's polarity masks for the next level
   int write_codes;        // store codes into the full-resolution array
-  int keep_clean;         // clean old vertices keep their stored code
   int dirty;              // test old vertices against the previous level
                           // (its masks from prev_masks if set, else from
                           // the field: the fused launches)
