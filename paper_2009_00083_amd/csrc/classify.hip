@@ -129,8 +129,8 @@ constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 // stride in dwords is odd, which keeps the per-row byte writes of the 64
 // lanes in distinct banks.
 constexpr int stage_dwords(int bytes) { return ((bytes + 3) / 4) | 1; }
-// 3D, for tiles of at most ZC planes: bytes of codes / u16 of masks per lane
-constexpr int code_stride3(int zc) { return 4 * stage_dwords(zc * kTile3Y); }
+// 3D, for tiles of at most ZC planes: u16 of masks per lane (codes are
+// staged row-major, 64 bytes per row)
 constexpr int mask_stride3(int zc) { return 2 * stage_dwords(2 * zc * kTile3Y); }
 constexpr int kCodeStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
 constexpr int kMaskStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
@@ -495,7 +495,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
           reclass += (unsigned)__popcll(dm);
         }
         const int q = qb + j;
-        stc[lane * code_stride3(ZC) + q] = (uint8_t)out;
+        stc[q * 64 + lane] = (uint8_t)out;
         if (WM && store_masks) stm[lane * mask_stride3(ZC) + q] = (uint16_t)mr[j];
         wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
         whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
@@ -548,49 +548,58 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     if (q < nrows && y < my)
       g.bits[((int64_t)z * my + y) * g.rowwords + tx] = wbits;
   }
-  if (!out_lane) return;
   // rows per plane that exist (the last row tile may stick out)
   const int nyl = min(R, my - y0);
   const int nzl = z1 - z0;
-  // this lane's staged codes, four rows per dword, read at once
   constexpr int NQ = ZC * R;
-  uint32_t cw[NQ / 4];
-  {
-    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stc + lane * code_stride3(ZC));
-#pragma unroll
-    for (int k = 0; k < NQ / 4; k++) cw[k] = sp[k];
-  }
-  auto staged = [&](int q) { return (cw[q >> 2] >> (8 * (q & 3))) & 0xFFu; };
-  if (g.write_codes) {
-    // full-resolution codes; plane pointer advanced per staged plane
-    const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
-    uint8_t *cp = a.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy;
-#pragma unroll
-    for (int zz = 0; zz < ZC; zz++, cp += g.sz) {
-      if (zz >= nzl) break;
-#pragma unroll
-      for (int j = 0; j < R; j++) {
-        if (j >= nyl) break;
-        st_u8(rsrc(cp + (int64_t)j * g.sy), xoffc, staged(zz * R + j));
-      }
+  const bool full_tile = x0 + 64 <= mx && nyl == R;  // wave-uniform
+  if (g.write_codes && g.sx == 1 && full_tile) {
+    // Codes are staged row-major (row q at stc[64 q]): one dword per lane
+    // covers four columns, a wave four rows, so each store instruction
+    // writes four 64-byte row segments.
+    // (rows written by other lanes of this wave: keep the reads after them)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stc);
+    static_assert(64 % R == 0, "a dword group of staged rows spans whole planes");
+    constexpr int PG = 4 / R;  // planes per group of four staged rows
+    // lane offset within a group: plane, row, four columns (< 4 GiB: a
+    // plane of codes is < 4 GiB and a group spans at most four rows)
+    const int qs = lane >> 4;
+    const uint32_t loff = (uint32_t)((qs / R) * g.sz + (qs % R) * g.sy) + 4u * (lane & 15);
+    const uint8_t *cb = a.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy + x0;
+#pragma unroll 4
+    for (int k = 0; k < NQ / 4; k++) {
+      if (k * PG >= nzl) break;
+      const uint32_t v = sp[k * 64 + lane];
+      if (PG * k + qs / R < nzl)
+        __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(cb + (int64_t)(PG * k) * g.sz), loff, 0, 0);
     }
   }
-  if (g.lcodes) {
-    uint8_t *lp = g.lcodes + ((int64_t)z0 * my + y0) * mx;
-    const int64_t lplane = (int64_t)my * mx;
-#pragma unroll
-    for (int zz = 0; zz < ZC; zz++, lp += lplane) {
-      if (zz >= nzl) break;
-#pragma unroll
-      for (int j = 0; j < R; j++) {
-        if (j >= nyl) break;
-        st_u8(rsrc(lp + (int64_t)j * mx), (uint32_t)x, staged(zz * R + j));
+  if (!out_lane) return;
+  // Strided levels, partial tiles and dense level codes: one byte per lane
+  // and row, in a loop that is not unrolled (these are the rare paths; an
+  // unrolled one would hoist every staged read into its own register).
+  if ((g.write_codes && !(g.sx == 1 && full_tile)) || g.lcodes) {
+    const bool full_res = g.write_codes && !(g.sx == 1 && full_tile);
+    const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
+#pragma unroll 1
+    for (int zz = 0; zz < nzl; zz++) {
+#pragma unroll 1
+      for (int j = 0; j < nyl; j++) {
+        const unsigned b = stc[(zz * R + j) * 64 + lane];
+        if (full_res)
+          st_u8(rsrc(a.codes + (int64_t)(z0 + zz) * g.sz + (int64_t)(y0 + j) * g.sy), xoffc, b);
+        if (g.lcodes)
+          st_u8(rsrc(g.lcodes + ((int64_t)(z0 + zz) * my + (y0 + j)) * mx), (uint32_t)x, b);
       }
     }
   }
   if (WM && store_masks) {
     // masks: two rows per dword, read in groups of NQ / 4 dwords
     const uint32_t *sp = reinterpret_cast<const uint32_t *>(stm + lane * mask_stride3(ZC));
+    uint32_t cw[NQ / 4];
     char *mp = reinterpret_cast<char *>(g.masks) + (((int64_t)z0 * my + y0) * mx) * 2;
     const int64_t mplane = (int64_t)my * mx * 2;
 #pragma unroll
@@ -820,7 +829,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   static_assert(ZC * R <= 64, "one critical word per lane");
   static_assert(ZC % 2 == 0, "mask staging in two halves");
   __shared__ __attribute__((aligned(16))) uint8_t slut[kLut3Size];
-  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * code_stride3(ZC)];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * ZC * R];
   __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? 64 * mask_stride3(ZC) : 2];
   __shared__ unsigned s_reclass[kMaxFused];
 
