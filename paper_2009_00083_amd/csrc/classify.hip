@@ -129,9 +129,6 @@ constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 // stride in dwords is odd, which keeps the per-row byte writes of the 64
 // lanes in distinct banks.
 constexpr int stage_dwords(int bytes) { return ((bytes + 3) / 4) | 1; }
-// 3D, for tiles of at most ZC planes: u16 of masks per lane (codes are
-// staged row-major, 64 bytes per row)
-constexpr int mask_stride3(int zc) { return 2 * stage_dwords(2 * zc * kTile3Y); }
 constexpr int kCodeStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
 constexpr int kMaskStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
 constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
@@ -496,7 +493,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
         }
         const int q = qb + j;
         stc[q * 64 + lane] = (uint8_t)out;
-        if (WM && store_masks) stm[lane * mask_stride3(ZC) + q] = (uint16_t)mr[j];
+        if (WM && store_masks) stm[q * 64 + lane] = (uint16_t)mr[j];
         wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
         whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
       }
@@ -552,15 +549,16 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   const int nyl = min(R, my - y0);
   const int nzl = z1 - z0;
   constexpr int NQ = ZC * R;
+  // the flush reads staged rows that other lanes of this wave wrote: keep
+  // those reads after the writes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const bool full_tile = x0 + 64 <= mx && nyl == R;  // wave-uniform
   if (g.write_codes && g.sx == 1 && full_tile) {
     // Codes are staged row-major (row q at stc[64 q]): one dword per lane
     // covers four columns, a wave four rows, so each store instruction
     // writes four 64-byte row segments.
-    // (rows written by other lanes of this wave: keep the reads after them)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint32_t *sp = reinterpret_cast<const uint32_t *>(stc);
     static_assert(64 % R == 0, "a dword group of staged rows spans whole planes");
     constexpr int PG = 4 / R;  // planes per group of four staged rows
@@ -597,26 +595,28 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     }
   }
   if (WM && store_masks) {
-    // masks: two rows per dword, read in groups of NQ / 4 dwords
-    const uint32_t *sp = reinterpret_cast<const uint32_t *>(stm + lane * mask_stride3(ZC));
-    uint32_t cw[NQ / 4];
-    char *mp = reinterpret_cast<char *>(g.masks) + (((int64_t)z0 * my + y0) * mx) * 2;
-    const int64_t mplane = (int64_t)my * mx * 2;
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-#pragma unroll
-      for (int k = 0; k < NQ / 4; k++) cw[k] = sp[h * (NQ / 4) + k];
-#pragma unroll
-      for (int zl = 0; zl < ZC / 2; zl++, mp += mplane) {
-        const int zz = h * (ZC / 2) + zl;
+    // Masks are staged row-major (row q at stm[64 q]).  Whole tiles of a
+    // level with an even row length: one dword per lane covers two columns,
+    // a wave two rows of one plane; otherwise one u16 per lane and row.
+    char *mb = reinterpret_cast<char *>(g.masks);
+    if (full_tile && !(mx & 1)) {
+      static_assert(R == 2, "a dword group of staged mask rows is one plane");
+      const uint32_t *sp = reinterpret_cast<const uint32_t *>(stm);
+      const uint32_t loff = (uint32_t)((lane >> 5) * mx * 2) + 4u * (lane & 31);
+      const char *pb = mb + (((int64_t)z0 * my + y0) * mx + x0) * 2;
+      const int64_t mplane = (int64_t)my * mx * 2;
+#pragma unroll 4
+      for (int zz = 0; zz < ZC; zz++) {
         if (zz >= nzl) break;
-#pragma unroll
-        for (int j = 0; j < R; j++) {
-          if (j >= nyl) break;
-          const int ql = zl * R + j;  // row within this group
-          const unsigned m = (cw[ql >> 1] >> (16 * (ql & 1))) & 0xFFFFu;
-          st_u16(rsrc(mp + (int64_t)j * mx * 2), (uint32_t)x * 2u, m);
-        }
+        __builtin_amdgcn_raw_buffer_store_b32(sp[zz * 64 + lane], rsrc(pb + zz * mplane), loff, 0, 0);
+      }
+    } else if (out_lane) {
+#pragma unroll 1
+      for (int zz = 0; zz < nzl; zz++) {
+#pragma unroll 1
+        for (int j = 0; j < nyl; j++)
+          st_u16(rsrc(mb + (((int64_t)(z0 + zz) * my + (y0 + j)) * mx) * 2), (uint32_t)x * 2u,
+                 stm[(zz * R + j) * 64 + lane]);
       }
     }
   }
@@ -830,7 +830,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify3d_kernel(
   static_assert(ZC % 2 == 0, "mask staging in two halves");
   __shared__ __attribute__((aligned(16))) uint8_t slut[kLut3Size];
   __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * ZC * R];
-  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? 64 * mask_stride3(ZC) : 2];
+  __shared__ __attribute__((aligned(16))) uint16_t smask[WM ? NW : 1][WM ? 64 * ZC * R : 2];
   __shared__ unsigned s_reclass[kMaxFused];
 
   // the wave index is the same in every lane: keep tile arithmetic scalar

@@ -55,8 +55,8 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kTile3Y = 2;    // rows per 3D wave tile
 constexpr int kZChunk3 = 24;  // planes per 3D wave tile
 // Launches that store masks stage twice as many bytes per vertex in LDS;
-// their tiles are shallower so that four blocks fit on a CU.
-constexpr int kZChunk3Masks = 12;
+// their tiles are shallower so that five blocks fit on a CU.
+constexpr int kZChunk3Masks = 8;
 constexpr int zchunk_cap3(bool write_masks) { return write_masks ? kZChunk3Masks : kZChunk3; }
 constexpr int kYChunk2 = 60;  // rows per 2D wave tile
 constexpr int kUnroll3 = 4;   // 3D march unroll (ring of planes in registers)
