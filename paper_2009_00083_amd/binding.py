@@ -9,6 +9,7 @@ fallback.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 from dataclasses import dataclass
 from typing import List, Optional
@@ -64,6 +65,7 @@ def _load():
                                    i64, p64, vp]
     lib.pcrit_classify.restype = i32
     lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
+    lib.NULL_CB = ctypes.cast(None, lib.LEVEL_CB)
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
                                       i64, vp, vp, vp, lib.LEVEL_CB, vp]
     lib.pcrit_progressive.restype = i32
@@ -115,6 +117,18 @@ def level_dims(shape, level: int):
     _check(_load().pcrit_level_dims(nx, ny, nz, level, m.ctypes.data),
            "level_dims")
     return tuple(int(v) for v in m)
+
+
+@functools.lru_cache(maxsize=64)
+def _hierarchy(shape):
+    """(k_max, vertices of all levels) of a grid shape (cached: the
+    progressive call is issued per step)."""
+    kmax = max_level(shape)
+    total = 0
+    for k in range(kmax + 1):
+        m = level_dims(shape, k)
+        total += m[0] * m[1] * m[2]
+    return kmax, total
 
 
 def link_table(dim: int) -> np.ndarray:
@@ -285,12 +299,9 @@ def progressive(field, *, ctx: Optional[Context] = None,
     nx, ny, nz = _check_field(field)
     lib = _load()
     c = _ctx_for(field, ctx)
-    kmax = max_level(field.shape)
+    kmax, total = _hierarchy(tuple(field.shape))
     if capacity is None:
-        capacity = 0
-        for k in range(kmax + 1):
-            m = level_dims(field.shape, k)
-            capacity += m[0] * m[1] * m[2]
+        capacity = total
     if codes is None:
         codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
     if crit is None:
@@ -302,7 +313,7 @@ def progressive(field, *, ctx: Optional[Context] = None,
     offs = np.zeros(kmax + 2, np.int64)
     ms = np.zeros(kmax + 1, np.float32) if level_times else None
     rec = np.zeros(kmax + 1, np.int64)
-    cb = lib.LEVEL_CB(callback) if callback else ctypes.cast(None, lib.LEVEL_CB)
+    cb = lib.LEVEL_CB(callback) if callback else lib.NULL_CB
     st = lib.pcrit_progressive(
         c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
         _ptr(codes), _ptr(crit), _ptr(crit_codes), int(capacity),
