@@ -1064,18 +1064,17 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
       tot += s_wtot[i];
     }
     {
-      // low half into [o, o + plo), high half into [o + plo, o + cnt)
+      // low half into [o, o + plo), then high half into [o + plo, o + cnt)
       const unsigned e0 = (unsigned)tid << 6;
-      int o = woff + incl - cnt, oh = o + plo;
-      while (lo | hi) {
-        if (lo) {
-          s_ent[o++] = (uint16_t)(e0 | (unsigned)__builtin_ctz(lo));
-          lo &= lo - 1u;
-        }
-        if (hi) {
-          s_ent[oh++] = (uint16_t)(e0 | 32u | (unsigned)__builtin_ctz(hi));
-          hi &= hi - 1u;
-        }
+      uint16_t *ep = s_ent + (woff + incl - cnt);
+      while (lo) {
+        *ep++ = (uint16_t)(e0 | (unsigned)__builtin_ctz(lo));
+        lo &= lo - 1u;
+      }
+      const unsigned e1 = e0 | 32u;
+      while (hi) {
+        *ep++ = (uint16_t)(e1 | (unsigned)__builtin_ctz(hi));
+        hi &= hi - 1u;
       }
     }
     __syncthreads();
@@ -1085,20 +1084,17 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
     uint32_t *dst = a.crit + out0;
     if (linear) {
       const uint32_t ibase = (uint32_t)(gw0 * 64);
+      // whole groups of UW * T entries without bounds tests, then the tail
       constexpr int UW = 4;
-      for (int e0 = 0; e0 < lim; e0 += UW * T) {
+      const int lim_full = lim - lim % (UW * T);
+      for (int e0 = 0; e0 < lim_full; e0 += UW * T) {
         uint32_t v[UW];
 #pragma unroll
-        for (int u = 0; u < UW; u++) {
-          const int e = e0 + u * T + tid;
-          v[u] = e < lim ? (uint32_t)s_ent[e] : 0u;
-        }
+        for (int u = 0; u < UW; u++) v[u] = s_ent[e0 + u * T + tid];
 #pragma unroll
-        for (int u = 0; u < UW; u++) {
-          const int e = e0 + u * T + tid;
-          if (e < lim) dst[e] = ibase + v[u];
-        }
+        for (int u = 0; u < UW; u++) dst[e0 + u * T + tid] = ibase + v[u];
       }
+      for (int e = lim_full + tid; e < lim; e += T) dst[e] = ibase + s_ent[e];
     } else {
       for (int e = tid; e < lim; e += T) {
         const unsigned ent = s_ent[e];
