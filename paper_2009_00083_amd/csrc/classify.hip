@@ -974,15 +974,26 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
   return x;
 }
 
-// expand_kernel: the chunk's words are loaded at once (WPT per thread) and
-// processed in WPT rounds of one word per thread.  In a round every thread
-// expands its word into LDS at its position (block scan of the popcounts) as
-// 16-bit entries (word << 6 | bit), the two 32-bit halves side by side, then
-// the block writes the round's entries to the list with coalesced stores.
-// Entries are in index order because words are in index order and bits are
-// expanded low to high.  On a linear level (full resolution, rows a whole
-// number of words) the index of an entry is 64 * (first word of the round)
-// + entry; otherwise it comes from the word's row start.
+// Orders this wave's LDS reads after its earlier LDS writes by other lanes
+// (a wave executes its LDS instructions in order; this only stops the
+// compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// expand_kernel: every wave owns a contiguous run of WPT * 64 words of the
+// chunk, loaded at once (one word per lane and round).  One block scan of
+// the waves' popcount totals places each wave's run; after that the waves
+// work on their own: in a round every lane expands its word into the wave's
+// LDS region at its position (DPP scan of the popcounts) as 16-bit entries
+// (word << 6 | bit), low half then high half, and the wave writes the
+// round's entries to the list with coalesced stores.  Entries are in index
+// order because words are in index order and bits are expanded low to high.
+// On a linear level (full resolution, rows a whole number of words) the
+// index of an entry is 64 * (first word of the round) + entry; otherwise it
+// comes from the word's row start.
 template <int WPT>
 __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) {
   constexpr int T = kCompactThreads;
@@ -990,19 +1001,19 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   constexpr int NWV = T / 64;
   __shared__ int64_t s_red[NWV];
   __shared__ int s_wtot[NWV];
-  __shared__ uint16_t s_ent[T * 64];
-  __shared__ uint32_t s_row0[T];
+  __shared__ uint16_t s_ent[NWV][64 * 64];
+  __shared__ uint32_t s_row0[NWV][64];
   const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = level_of_chunk(a, chunk);
   const CompactLevel &L = a.lv[li];
   const int lchunk = chunk - L.chunk_begin;
-  const int64_t wfirst = (int64_t)lchunk * CW;
-  // this thread's words: wfirst + k*T + tid, all loads issued up front
+  // first word of this wave's run
+  const int64_t wrun = (int64_t)lchunk * CW + (int64_t)w * (64 * WPT);
   uint64_t wd[WPT];
 #pragma unroll
   for (int k = 0; k < WPT; k++) {
-    const int64_t gw = wfirst + (int64_t)k * T + tid;
+    const int64_t gw = wrun + (int64_t)k * 64 + lane;
     wd[k] = gw < L.words ? L.bits[gw] : 0ull;
   }
   // entries before this chunk, and before this chunk's level, in this launch
@@ -1034,39 +1045,45 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
     a.reclass_acc[li] = 0u;
     if (L.reclass_out) *L.reclass_out = r;
   }
+  // this wave's place in the chunk
+  int cnt_all = 0;
+#pragma unroll
+  for (int k = 0; k < WPT; k++) cnt_all += __popcll(wd[k]);
+  const int wtot = __builtin_amdgcn_readlane(wave_inclusive_sum(cnt_all), 63);
+  if (lane == 0) s_wtot[w] = wtot;
+  __syncthreads();
+  int woff = 0, ctot = 0;
+#pragma unroll
+  for (int i = 0; i < NWV; i++) {
+    woff += i < w ? s_wtot[i] : 0;
+    ctot += s_wtot[i];
+  }
 
   const bool linear = L.linear && !a.crit_codes;
   const int64_t rowstep = L.s * a.nx;
   const uint32_t s = (uint32_t)L.s;
-  int64_t done = 0;  // entries of this chunk written so far
+  uint16_t *went = s_ent[w];
+  int64_t out0 = base + prefix + woff;  // list position of the round's first entry
 #pragma unroll
   for (int k = 0; k < WPT; k++) {
-    const int64_t gw0 = wfirst + (int64_t)k * T;  // first word of the round
+    const int64_t gw0 = wrun + (int64_t)k * 64;  // first word of the round
     uint32_t lo = (uint32_t)wd[k], hi = (uint32_t)(wd[k] >> 32);
-    const int plo = __popc(lo);
-    const int cnt = plo + __popc(hi);
+    const int cnt = __popc(lo) + __popc(hi);
     const int incl = wave_inclusive_sum(cnt);
-    if (lane == 63) s_wtot[w] = incl;
+    const int tot = __builtin_amdgcn_readlane(incl, 63);
     if (!linear && (lo | hi)) {
       // word gw covers columns 64*xw + bit of level row r
-      const uint32_t gw = (uint32_t)(gw0 + tid);
+      const uint32_t gw = (uint32_t)(gw0 + lane);
       const uint32_t r = gw / (uint32_t)L.rowwords;
       const uint32_t xw = gw - r * (uint32_t)L.rowwords;
       const uint32_t zz = r / (uint32_t)L.my, yy = r - zz * (uint32_t)L.my;
-      s_row0[tid] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
-                               L.s * (int64_t)xw * kTileCols);
-    }
-    __syncthreads();
-    int woff = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < NWV; i++) {
-      woff += i < w ? s_wtot[i] : 0;
-      tot += s_wtot[i];
+      s_row0[w][lane] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
+                                   L.s * (int64_t)xw * kTileCols);
     }
     {
-      // low half into [o, o + plo), then high half into [o + plo, o + cnt)
-      const unsigned e0 = (unsigned)tid << 6;
-      uint16_t *ep = s_ent + (woff + incl - cnt);
+      // low half, then high half, from this lane's position
+      const unsigned e0 = (unsigned)lane << 6;
+      uint16_t *ep = went + (incl - cnt);
       while (lo) {
         *ep++ = (uint16_t)(e0 | (unsigned)__builtin_ctz(lo));
         lo &= lo - 1u;
@@ -1077,28 +1094,27 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
         hi &= hi - 1u;
       }
     }
-    __syncthreads();
-    const int64_t out0 = base + prefix + done;
+    wave_lds_sync();
     // entries of this round that fit the capacity
     const int lim = (int)max((int64_t)0, min((int64_t)tot, a.cap - out0));
     uint32_t *dst = a.crit + out0;
     if (linear) {
       const uint32_t ibase = (uint32_t)(gw0 * 64);
-      // whole groups of UW * T entries without bounds tests, then the tail
+      // whole groups of UW * 64 entries without bounds tests, then the tail
       constexpr int UW = 4;
-      const int lim_full = lim - lim % (UW * T);
-      for (int e0 = 0; e0 < lim_full; e0 += UW * T) {
+      const int lim_full = lim - lim % (UW * 64);
+      for (int e0 = 0; e0 < lim_full; e0 += UW * 64) {
         uint32_t v[UW];
 #pragma unroll
-        for (int u = 0; u < UW; u++) v[u] = s_ent[e0 + u * T + tid];
+        for (int u = 0; u < UW; u++) v[u] = went[e0 + u * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < UW; u++) dst[e0 + u * T + tid] = ibase + v[u];
+        for (int u = 0; u < UW; u++) dst[e0 + u * 64 + lane] = ibase + v[u];
       }
-      for (int e = lim_full + tid; e < lim; e += T) dst[e] = ibase + s_ent[e];
+      for (int e = lim_full + lane; e < lim; e += 64) dst[e] = ibase + went[e];
     } else {
-      for (int e = tid; e < lim; e += T) {
-        const unsigned ent = s_ent[e];
-        const uint32_t idx = s_row0[ent >> 6] + s * (ent & 63u);
+      for (int e = lane; e < lim; e += 64) {
+        const unsigned ent = went[e];
+        const uint32_t idx = s_row0[w][ent >> 6] + s * (ent & 63u);
         dst[e] = idx;
         if (a.crit_codes) {
           uint8_t code;
@@ -1115,15 +1131,15 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
         }
       }
     }
-    done += tot;
-    __syncthreads();
+    out0 += tot;
+    wave_lds_sync();  // the next round overwrites this wave's entries
   }
 
   // the first chunk of a later level opens its list, the last chunk of the
   // launch closes the last one
   if (li > 0 && lchunk == 0 && tid == 0) a.level_base[L.slot] = base + prefix;
   if (chunk == a.nchunks - 1 && tid == 0) {
-    const int64_t total = prefix + done;
+    const int64_t total = prefix + ctot;
     a.level_base[L.slot + 1] = base + total;
     if (a.count_dev)
       *a.count_dev = (*a.nan_flag == a.gen) ? -1 : total - lprefix;
