@@ -101,36 +101,39 @@ constexpr unsigned AYM2 = side_mask2(1, -1), AYP2 = side_mask2(1, 1);
 // ---------------------------------------------------------------------------
 // Shared structure of the classification kernels
 // ---------------------------------------------------------------------------
-// * Every wave owns a tile: a window of 64 consecutive x (one sample per
-//   lane) by R rows (3D) or one row (2D), marched along the slowest axis.
-//   Lanes 1..62 are classified; lanes 0 and 63 only hold the x-1 / x+1
-//   neighbours of lanes 1 and 62.  The waves of a block share only the
-//   link-pattern table, so there is no block barrier inside the march.
+// * Every wave owns a tile: 64 consecutive x (one sample per lane) by R rows
+//   (3D) or a run of rows (2D), marched along the slowest axis.  The
+//   columns left and right of the tile come from one packed halo load per
+//   plane (row) and are shifted in at lanes 0 and 63.  The waves of a block
+//   share only the link-pattern table, so there is no block barrier inside
+//   the march.
 // * The samples of the planes (rows) around the current one stay in
 //   registers.  x-1 and x+1 neighbours are read from the lanes next door by
-//   a DPP wave shift that the compiler folds into the subtraction itself.
+//   DPP wave shifts.
 // * A polarity bit is the sign of one float difference, appended to the mask
 //   with one alignbit.  For a centre c that is finite and non-zero the sign
 //   of c - n (or n - c) is exact, ties included; a step in which some lane's
 //   centre is +-0, +-inf or NaN recomputes its masks by exact comparisons.
 // * Loads use a scalar plane (row) base and a 32-bit lane offset.  The march
-//   issues loads only (planes kept three ahead): on this architecture loads
-//   and stores share one completion counter, and with a store in flight the
-//   compiler can no longer wait for one particular load, so codes and masks
-//   are staged in LDS and written after the tile.
-// * Persistent blocks walk the tile list; the tiles of one XCD form a
-//   contiguous run, so neighbouring tiles (which share halo rows) meet in
-//   the same L2.  A launch may cover several small levels (the progressive
+//   issues loads only: on this architecture loads and stores share one
+//   completion counter, and with a store in flight the compiler can no
+//   longer wait for one particular load, so codes and masks are staged in
+//   LDS (row-major) and written after the tile, several columns per lane.
+// * A launch gives every wave one or two tiles; the tiles of one XCD form a
+//   contiguous run, so neighbouring tiles (which share halo rows) meet in the
+//   same L2.  A launch may cover several small levels (the progressive
 //   driver fuses the latency-bound coarse levels); a wave then looks up the
 //   level of its tile in the launch's level table.
 
-// LDS staging of a wave's tile, lane-major: lane l's staged rows are
-// contiguous at l * stride, so the flush reads four rows per dword.  The
-// stride in dwords is odd, which keeps the per-row byte writes of the 64
-// lanes in distinct banks.
-constexpr int stage_dwords(int bytes) { return ((bytes + 3) / 4) | 1; }
-constexpr int kCodeStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
-constexpr int kMaskStride2 = 4 * stage_dwords(kYChunk2);     // bytes per lane
+// Orders this wave's LDS reads after its earlier LDS writes by other lanes
+// (a wave executes its LDS instructions in order; this only stops the
+// compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- lane i reads lane i+1
 constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- lane i reads lane i-1
 
@@ -549,11 +552,8 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   const int nyl = min(R, my - y0);
   const int nzl = z1 - z0;
   constexpr int NQ = ZC * R;
-  // the flush reads staged rows that other lanes of this wave wrote: keep
-  // those reads after the writes
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // the flush reads staged rows that other lanes of this wave wrote
+  wave_lds_sync();
   const bool full_tile = x0 + 64 <= mx && nyl == R;  // wave-uniform
   if (g.write_codes && g.sx == 1 && full_tile) {
     // Codes are staged row-major (row q at stc[64 q]): one dword per lane
@@ -743,8 +743,8 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
       reclass += (unsigned)__popcll(dm);
     }
     const int q = y - y0;
-    stc[lane * kCodeStride2 + q] = (uint8_t)out;
-    if (WM && store_masks) stm[lane * kMaskStride2 + q] = (uint8_t)m;
+    stc[q * 64 + lane] = (uint8_t)out;
+    if (WM && store_masks) stm[q * 64 + lane] = (uint8_t)m;
     wlo = (unsigned)pcrit_writelane((int)crit, q, (int)wlo);
     whi = (unsigned)pcrit_writelane((int)(crit >> 32), q, (int)whi);
   };
@@ -769,41 +769,41 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const int nrows = y1 - y0;
   const uint64_t wbits = (((uint64_t)whi << 32) | wlo) & out_lanes;
   if (lane < nrows) g.bits[(int64_t)(y0 + lane) * g.rowwords + tx] = wbits;
-  if (!out_lane) return;
-  constexpr int NQ = kYChunk2;
-  constexpr int ND = (NQ + 3) / 4;
-  uint32_t cw[ND];
-  auto read_stage = [&](const uint8_t *base, int stride) {
-    const uint32_t *sp = reinterpret_cast<const uint32_t *>(base + lane * stride);
-#pragma unroll
-    for (int k = 0; k < ND; k++) cw[k] = sp[k];
+  // Codes and masks are staged row-major (row q at 64 q).  Whole tiles with
+  // aligned rows: one dword per lane covers four columns, a wave four rows;
+  // otherwise one byte per lane and row in a rolled loop.
+  wave_lds_sync();
+  const bool full_tile = x0 + 64 <= mx;  // wave-uniform
+  auto rows4 = [&](const uint8_t *st, uint8_t *base, int64_t rstride) {
+    const uint32_t *sp = reinterpret_cast<const uint32_t *>(st);
+    const int qs = lane >> 4;
+    const uint32_t loff = (uint32_t)(qs * rstride) + 4u * (lane & 15);
+#pragma unroll 4
+    for (int k = 0; k < kYChunk2 / 4; k++) {
+      if (4 * k >= nrows) break;
+      const uint32_t v = sp[k * 64 + lane];
+      if (4 * k + qs < nrows)
+        __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(base + (int64_t)(4 * k) * rstride),
+                                              loff, 0, 0);
+    }
   };
-  auto staged = [&](int q) { return (cw[q >> 2] >> (8 * (q & 3))) & 0xFFu; };
-  read_stage(stc, kCodeStride2);
-  if (g.write_codes) {
+  const bool codes4 = g.write_codes && g.sx == 1 && full_tile && !(g.sy & 3);
+  if (codes4) rows4(stc, a.codes + (int64_t)y0 * g.sy + x0, g.sy);
+  const bool masks4 = WM && store_masks && full_tile && !(mx & 3);
+  if (masks4) rows4(stm, reinterpret_cast<uint8_t *>(g.masks) + (int64_t)y0 * mx + x0, mx);
+  if (!out_lane) return;
+  const bool codes1 = g.write_codes && !codes4;
+  const bool masks1 = WM && store_masks && !masks4;
+  if (codes1 || masks1 || g.lcodes) {
     const uint32_t xoffc = (uint32_t)((int64_t)x * g.sx);
-    uint8_t *cp = a.codes + (int64_t)y0 * g.sy;
-#pragma unroll
-    for (int q = 0; q < NQ; q++, cp += g.sy) {
-      if (q >= nrows) break;
-      st_u8(rsrc(cp), xoffc, staged(q));
-    }
-  }
-  if (g.lcodes) {
-    uint8_t *lp = g.lcodes + (int64_t)y0 * mx;
-#pragma unroll
-    for (int q = 0; q < NQ; q++, lp += mx) {
-      if (q >= nrows) break;
-      st_u8(rsrc(lp), (uint32_t)x, staged(q));
-    }
-  }
-  if (WM && store_masks) {
-    read_stage(stm, kMaskStride2);
-    char *mp = reinterpret_cast<char *>(g.masks) + (int64_t)y0 * mx;
-#pragma unroll
-    for (int q = 0; q < NQ; q++, mp += mx) {
-      if (q >= nrows) break;
-      st_u8(rsrc(mp), (uint32_t)x, staged(q));
+#pragma unroll 1
+    for (int q = 0; q < nrows; q++) {
+      const unsigned b = stc[q * 64 + lane];
+      if (codes1) st_u8(rsrc(a.codes + (int64_t)(y0 + q) * g.sy), xoffc, b);
+      if (g.lcodes) st_u8(rsrc(g.lcodes + (int64_t)(y0 + q) * mx), (uint32_t)x, b);
+      if (masks1)
+        st_u8(rsrc(reinterpret_cast<uint8_t *>(g.masks) + (int64_t)(y0 + q) * mx),
+              (uint32_t)x, stm[q * 64 + lane]);
     }
   }
 }
@@ -876,8 +876,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void classify2d_kernel(
   constexpr int YC = kYChunk2;
   static_assert(YC % kUnroll2 == 0 && YC <= 64, "tile depth");
   __shared__ uint8_t slut[kLut2Size];
-  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * kCodeStride2];
-  __shared__ __attribute__((aligned(16))) uint8_t smask[WM ? NW : 1][WM ? 64 * kMaskStride2 : 4];
+  __shared__ __attribute__((aligned(16))) uint8_t scode[NW][64 * kYChunk2];
+  __shared__ __attribute__((aligned(16))) uint8_t smask[WM ? NW : 1][WM ? 64 * kYChunk2 : 4];
   __shared__ unsigned s_reclass[kMaxFused];
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -972,15 +972,6 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
   x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
   x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
   return x;
-}
-
-// Orders this wave's LDS reads after its earlier LDS writes by other lanes
-// (a wave executes its LDS instructions in order; this only stops the
-// compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // expand_kernel: every wave owns a contiguous run of WPT * 64 words of the

@@ -304,6 +304,35 @@ def test_progressive_unfused_and_reclassified(ctx, dev, shape, gen):
     check_progressive(ctx, dev, f)
 
 
+@pytest.mark.parametrize("shape", [(130, 130, 257), (130, 132, 256)])
+@pytest.mark.parametrize("callback", [False, True])
+def test_progressive_without_list_codes(ctx, dev, shape, callback):
+    """Without crit_codes only the last level stores full-resolution codes.
+    Grids above 2^22 vertices give level 0 a launch of its own that reads the
+    masks the coarser launch stored (level-1 rows of odd and even length, so
+    both mask write-outs run; whole and partial 64-column tiles, so both code
+    write-outs run).  Every level's list equals the direct classification of
+    that level, and the codes equal the direct level-0 codes and the
+    oracle's."""
+    f = fieldgen.gaussian_field(shape, 16, 11, noise=("uniform", 1e-3))
+    ft = torch.from_numpy(f).to(dev)
+    log(f"progressive without list codes {shape} callback={callback}")
+    cb = (lambda k, n, u: None) if callback else None
+    p = pc.progressive(ft, ctx=ctx, callback=cb)
+    torch.cuda.synchronize()
+    assert p.status == 0 and p.crit_codes is None
+    crit_all = p.crit.cpu().numpy().view(np.uint32)
+    for i, k in enumerate(p.levels):
+        d = pc.classify(ft, k, ctx=ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(crit_all[p.offsets[i]:p.offsets[i + 1]],
+                              d.crit.cpu().numpy().view(np.uint32)), f"level {k}"
+    ref = oracle.classify(f, level=0)
+    codes = p.codes.cpu().numpy()
+    assert np.array_equal(codes, ref.codes)
+    assert np.array_equal(crit_all[p.offsets[-2]:p.offsets[-1]], ref.crit)
+
+
 def test_progressive_special_values(ctx, dev):
     f = fieldgen.tie_field((21, 22, 23), 9, 4)
     vals = np.array([-np.inf, -0.0, 0.0, np.inf, 1.0], np.float32)
