@@ -6,7 +6,9 @@ vertices whose polarity changed) and compacted into its ascending critical
 list.  The field is resident in HBM before the timed region.
 
 Prints one JSON line.  value = vertices of all levels / ms_per_step, in
-Gvertices/s.  Extra keys: time_to_exact_ms (first enqueue to level-0
+Gvertices/s, with the steps enqueued back to back through the asynchronous
+entry point; ms_per_step_sync is the same loop through the synchronous one
+(the host waits for every step).  Extra keys: time_to_exact_ms (first enqueue to level-0
 completion, stream events), preview F1 at 10 % of that time, the direct
 level-0 rate, per-level rates, the roofline of the dominant kernel, and the
 CPU oracle's rate on a bounded sample of the same workload.
@@ -106,20 +108,37 @@ def main():
         return pc.progressive(ft, ctx=ctx, capacity=cap, codes=codes, crit=crit,
                               level_times=level_times)
 
+    offs_dev = torch.empty(len(levels) + 1, dtype=torch.int64, device=dev)
+
+    def step_async():
+        pc.progressive_async(ft, ctx=ctx, capacity=cap, codes=codes, crit=crit,
+                             offsets=offs_dev)
+
     for _ in range(args.warmup):
         step()
+        step_async()
     torch.cuda.synchronize()
 
-    # timed region A: the whole hot path, no events inside
+    # timed region A: the whole hot path, steps enqueued back to back (the
+    # asynchronous entry point), no events inside
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_async()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = total_v / (ms_per_step * 1e-3) / 1e9
+
+    # region S: the synchronous entry point (host waits for every step)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = step()
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    ms_per_step_sync = (time.perf_counter() - t0) * 1e3 / args.steps
     assert r.status == 0
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = total_v / (ms_per_step * 1e-3) / 1e9
+    assert np.array_equal(offs_dev.cpu().numpy(), r.offsets)
 
     # region T: the same steps with a completion event per launch; time to
     # exact = first kernel to level-0 completion (stream events)
@@ -213,6 +232,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_sync": round(ms_per_step_sync, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

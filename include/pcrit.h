@@ -175,6 +175,22 @@ int pcrit_progressive(pcrit_ctx *ctx, void *hip_stream, const float *field,
                       float *level_ms_host, int64_t *reclassified_host,
                       pcrit_level_cb cb, void *user);
 
+/* The same progressive classification, enqueued without any host
+ * synchronisation (for pipelines that issue one call after another on a
+ * stream and look at the results later): no list codes, timing or callback.
+ *   level_offsets_dev  device, k_max+2 int64 (8-byte aligned): written
+ *                 asynchronously when the call's work completes, as
+ *                 level_offsets_host of pcrit_progressive; the last entry is
+ *                 -1 if a NaN sample was found.  An entry above
+ *                 crit_capacity means the lists did not fit (only the first
+ *                 crit_capacity entries are written).
+ * Returns PCRIT_OK once the work is enqueued, or an argument / HIP error
+ * (nothing enqueued).  Calls on one context must share one stream. */
+int pcrit_progressive_async(pcrit_ctx *ctx, void *hip_stream, const float *field,
+                            int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
+                            uint32_t *crit, int64_t crit_capacity,
+                            int64_t *level_offsets_dev);
+
 /* Measurement.  Every later call records a HIP event pair on its stream
  * around the classification kernel and around the compaction kernels of
  * each level k whose bit k is set in level_mask (0 disables; the records

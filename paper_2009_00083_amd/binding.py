@@ -24,8 +24,8 @@ _lib = None
 
 EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_max_level", "pcrit_level_dims", "pcrit_link_table",
-            "pcrit_classify", "pcrit_progressive", "pcrit_set_kernel_timing",
-            "pcrit_kernel_ms", "pcrit_preview_f1")
+            "pcrit_classify", "pcrit_progressive", "pcrit_progressive_async",
+            "pcrit_set_kernel_timing", "pcrit_kernel_ms", "pcrit_preview_f1")
 
 
 class PcritError(RuntimeError):
@@ -69,6 +69,8 @@ def _load():
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
                                       i64, vp, vp, vp, lib.LEVEL_CB, vp]
     lib.pcrit_progressive.restype = i32
+    lib.pcrit_progressive_async.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, vp]
+    lib.pcrit_progressive_async.restype = i32
     lib.pcrit_set_kernel_timing.argtypes = [vp, ctypes.c_uint64]
     lib.pcrit_set_kernel_timing.restype = i32
     lib.pcrit_kernel_ms.argtypes = [vp, vp, vp, i32]
@@ -323,6 +325,34 @@ def progressive(field, *, ctx: Optional[Context] = None,
         raise PcritError(st, "pcrit_progressive")
     return ProgressiveResult(codes, crit, crit_codes,
                              list(range(kmax, -1, -1)), offs, ms, rec, st)
+
+
+def progressive_async(field, *, ctx: Optional[Context] = None,
+                      capacity: Optional[int] = None, codes=None, crit=None,
+                      offsets=None, stream=None):
+    """Enqueue a progressive classification without host synchronisation.
+
+    Returns (codes, crit, offsets): offsets is a device int64 tensor of
+    k_max+2 entries, valid once the stream reaches the end of the call's
+    work (its last entry is -1 if the field had a NaN sample)."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    lib = _load()
+    c = _ctx_for(field, ctx)
+    kmax, total = _hierarchy(tuple(field.shape))
+    if capacity is None:
+        capacity = total
+    if codes is None:
+        codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
+    if crit is None:
+        crit = torch.empty(max(capacity, 1), dtype=torch.int32, device=field.device)
+    if offsets is None:
+        offsets = torch.empty(kmax + 2, dtype=torch.int64, device=field.device)
+    _check(lib.pcrit_progressive_async(
+        c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
+        _ptr(codes), _ptr(crit), int(capacity), _ptr(offsets)),
+        "pcrit_progressive_async")
+    return codes, crit, offsets
 
 
 def preview_f1(shape, level: int, preview, preview_codes, exact, exact_codes):

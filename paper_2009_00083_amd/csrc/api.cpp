@@ -434,12 +434,18 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
   return count > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
 
-int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
-                      int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
-                      uint32_t *crit, uint8_t *crit_codes,
-                      int64_t crit_capacity, int64_t *level_offsets_host,
-                      float *level_ms_host, int64_t *reclassified_host,
-                      pcrit_level_cb cb, void *user) {
+}  // extern "C"
+
+namespace {
+
+// Plans and enqueues a progressive call (levels k_max .. 0) on `s`: level
+// steps, their grouping into launches, scratch sizing, then the launches.
+// With a callback every level completes (and is reported) on its own.
+int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
+                        int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
+                        uint32_t *crit, uint8_t *crit_codes, int64_t crit_capacity,
+                        bool timed, pcrit_level_cb cb, void *user, int *kmax_out,
+                        int *group_end, unsigned *gen_out) {
   if (!c || !field || !codes || crit_capacity < 0 ||
       (crit_capacity > 0 && !crit))
     return PCRIT_E_ARG;
@@ -448,13 +454,13 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   int st = check_dims(nx, ny, nz);
   if (st) return st;
   const int kmax = max_level_of(nx, ny, nz);
+  *kmax_out = kmax;
   Geom geo[kMaxLevels];
   for (int k = 0; k <= kmax; k++) {
     st = make_geom(nx, ny, nz, k, &geo[k]);
     if (st) return st;
   }
   if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
-  hipStream_t s = (hipStream_t)hip_stream;
 
   // Steps in order (i = kmax - k) and their grouping into launches: the
   // leading run of small levels is fused (up to kMaxFused per launch) unless
@@ -472,7 +478,6 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
       sp.reclass_out = &c->flags[3 + i];
     }
   }
-  int group_end[kMaxLevels];  // launch of step i covers [i, group_end[i])
   for (int i = 0; i <= kmax;) {
     int j = i + 1;
     if (!cb && level_vertices(steps[i].g) <= kSmallLevel)
@@ -516,7 +521,6 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   // Completion events only when asked for: every record is a release on the
   // stream, which costs microseconds of GPU time.  Levels of one launch
   // complete together and share the event of its last level.
-  const bool timed = level_ms_host != nullptr;
   if (timed && hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
@@ -530,6 +534,27 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
       cb(kmax - i, c->h_base[i + 1] - c->h_base[i], user);
     }
   }
+  *gen_out = gen;
+  return PCRIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
+                      int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
+                      uint32_t *crit, uint8_t *crit_codes,
+                      int64_t crit_capacity, int64_t *level_offsets_host,
+                      float *level_ms_host, int64_t *reclassified_host,
+                      pcrit_level_cb cb, void *user) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  int kmax = 0, group_end[kMaxLevels];
+  unsigned gen = 0;
+  const bool timed = level_ms_host != nullptr;
+  int st = enqueue_progressive(c, s, field, nx, ny, nz, codes, crit, crit_codes,
+                               crit_capacity, timed, cb, user, &kmax, group_end, &gen);
+  if (st) return st;
   if (read_status(c, s)) return PCRIT_E_HIP;
   if (level_offsets_host)
     for (int i = 0; i <= kmax + 1; i++) level_offsets_host[i] = c->h_base[i];
@@ -546,6 +571,24 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
     }
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
   return c->h_base[kmax + 1] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
+}
+
+int pcrit_progressive_async(pcrit_ctx *c, void *hip_stream, const float *field,
+                            int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
+                            uint32_t *crit, int64_t crit_capacity,
+                            int64_t *level_offsets_dev) {
+  if (!level_offsets_dev || misaligned(level_offsets_dev, 8)) return PCRIT_E_ARG;
+  hipStream_t s = (hipStream_t)hip_stream;
+  int kmax = 0, group_end[kMaxLevels];
+  unsigned gen = 0;
+  int st = enqueue_progressive(c, s, field, nx, ny, nz, codes, crit, nullptr,
+                               crit_capacity, false, nullptr, nullptr, &kmax,
+                               group_end, &gen);
+  if (st) return st;
+  return launch_publish_offsets(c->level_base, kmax + 2, &c->flags[0], gen,
+                                level_offsets_dev, s) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
 }
 
 int pcrit_set_kernel_timing(pcrit_ctx *c, uint64_t level_mask) {

@@ -961,6 +961,15 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(CompactArgs a) {
   if (tid == 0) a.counts[chunk] = tot;
 }
 
+// The list offsets of a call for the caller (device), the total -1 after a
+// NaN sample.
+__global__ __launch_bounds__(64) void publish_kernel(const int64_t *level_base, int n,
+                                                     const unsigned *nan_flag,
+                                                     unsigned gen, int64_t *out) {
+  const int i = threadIdx.x;
+  if (i < n) out[i] = (i == n - 1 && *nan_flag == gen) ? -1 : level_base[i];
+}
+
 // Inclusive prefix sum over the lanes of a wave: shifts within the 16-lane
 // DPP rows, then the row broadcasts of lanes 15 and 31.  Lanes without a
 // source add the `old` operand, 0.
@@ -1211,6 +1220,15 @@ hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
   if (write_masks)
     return launch_tiles<classify2d_kernel<false, true, false>>(a, st);
   return launch_tiles<classify2d_kernel<false, false, false>>(a, st);
+}
+
+hipError_t launch_publish_offsets(const int64_t *level_base, int n,
+                                  const unsigned *nan_flag, unsigned gen,
+                                  int64_t *out, hipStream_t st) {
+  if (n < 1 || n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(64), 0, st, level_base, n, nan_flag,
+                     gen, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st) {

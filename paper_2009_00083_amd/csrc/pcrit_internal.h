@@ -163,6 +163,11 @@ constexpr int64_t kSmallLaunchWords = int64_t(1) << 19;
 inline bool small_chunks(int64_t launch_words) { return launch_words <= kSmallLaunchWords; }
 
 // Launchers.
+// Copies the n list offsets to out (device), the last one -1 if the NaN flag
+// holds gen.
+hipError_t launch_publish_offsets(const int64_t *level_base, int n,
+                                  const unsigned *nan_flag, unsigned gen,
+                                  int64_t *out, hipStream_t st);
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
                            bool write_masks, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st);

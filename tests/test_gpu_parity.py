@@ -333,6 +333,49 @@ def test_progressive_without_list_codes(ctx, dev, shape, callback):
     assert np.array_equal(crit_all[p.offsets[-2]:p.offsets[-1]], ref.crit)
 
 
+@pytest.mark.parametrize("shape", [(37, 23, 19), (130, 130, 257), (301, 77)])
+def test_progressive_async_matches_sync(ctx, dev, shape):
+    """The asynchronous call enqueues the same work: after several calls in
+    a row (no host synchronisation between them) its device offsets, lists
+    and codes equal the synchronous call's."""
+    f = fieldgen.gaussian_field(shape, 16, 13, noise=("uniform", 1e-3))
+    ft = torch.from_numpy(f).to(dev)
+    log(f"progressive async {shape}")
+    p = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    codes, crit, offs = None, None, None
+    for _ in range(3):
+        codes, crit, offs = pc.progressive_async(ft, ctx=ctx, codes=codes, crit=crit,
+                                                 offsets=offs)
+    torch.cuda.synchronize()
+    o = offs.cpu().numpy()
+    assert np.array_equal(o, p.offsets)
+    n = int(o[-1])
+    assert torch.equal(crit[:n], p.crit[:n])
+    assert torch.equal(codes, p.codes)
+
+
+def test_progressive_async_nan_and_capacity(ctx, dev):
+    f = fieldgen.gaussian_field((20, 21, 66), 8, 5, noise=("uniform", 1e-3))
+    ft = torch.from_numpy(f).to(dev)
+    p = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    total = int(p.offsets[-1])
+    cap = total // 2
+    crit = torch.full((cap,), -7, dtype=torch.int32, device=dev)
+    _, crit, offs = pc.progressive_async(ft, ctx=ctx, capacity=cap, crit=crit)
+    torch.cuda.synchronize()
+    o = offs.cpu().numpy()
+    assert np.array_equal(o, p.offsets) and o[-1] > cap
+    assert torch.equal(crit, p.crit[:cap])
+    g = f.copy()
+    g[3, 4, 5] = np.nan
+    gt = torch.from_numpy(g).to(dev)
+    _, _, offs = pc.progressive_async(gt, ctx=ctx)
+    torch.cuda.synchronize()
+    assert int(offs[-1].item()) == -1
+
+
 def test_progressive_special_values(ctx, dev):
     f = fieldgen.tie_field((21, 22, 23), 9, 4)
     vals = np.array([-np.inf, -0.0, 0.0, np.inf, 1.0], np.float32)
