@@ -189,24 +189,8 @@ __device__ __forceinline__ void st_u16(__amdgpu_buffer_rsrc_t r, uint32_t off, u
 // Level-(k+1) raw polarity mask of an old vertex, from its neighbours two
 // level-k steps away (for levels classified in the same launch as the
 // previous one, whose masks are then not stored).  Positions off the grid
-// are clamped: their bits are masked by the caller.
-__device__ __forceinline__ unsigned far_mask3(const float *f,
-                                              const LevelDesc &g, int x,
-                                              int y, int z, float c) {
-  float v[14];
-#pragma unroll
-  for (int j = 0; j < 14; j++) {
-    const int xx = min(max(x + 2 * kOff3[j][0], 0), g.mx - 1);
-    const int yy = min(max(y + 2 * kOff3[j][1], 0), g.my - 1);
-    const int zz = min(max(z + 2 * kOff3[j][2], 0), g.mz - 1);
-    v[j] = f[(int64_t)xx * g.sx + (int64_t)yy * g.sy + (int64_t)zz * g.sz];
-  }
-  const float lo[4] = {v[0], v[1], v[2], v[3]};
-  const float mid[6] = {v[4], v[5], v[6], v[7], v[8], v[9]};
-  const float hi[4] = {v[10], v[11], v[12], v[13]};
-  return mask3(c, lo, mid, hi) ^ kPos3;
-}
-
+// are clamped: their bits are masked by the caller.  (3D: inside the tile
+// march.)
 __device__ __forceinline__ unsigned far_mask2(const float *f,
                                               const LevelDesc &g, int x,
                                               int y, float c) {
@@ -364,8 +348,42 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     for (int k = 0; k < R / 2; k++)
       pmoff[k] = (uint32_t)(((int64_t)min((y0 >> 1) + k, g.pmy - 1) * g.pmx + pxc) * 2);
   }
+  // x offsets of the previous level's neighbours x-2, x, x+2 (clamped: the
+  // bits of absent neighbours are masked by the dirty test)
+  uint32_t fxo[FAR ? 3 : 1];
+  if (FAR) {
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+      fxo[d] = (uint32_t)((int64_t)min(max(xc + 2 * (d - 1), 0), mx - 1) * g.sx * 4);
+  }
   // plane z of the field / of the previous level's masks, z clamped
   auto plane_at = [&](int z) { return fb + (int64_t)min(max(z, 0), mz - 1) * szb; };
+  // Previous-level raw mask of the old vertices of row (y, z), centre c:
+  // its neighbours two level steps away, one buffer load each (plane base
+  // and row offset scalar, column offset per lane), bits by the sign of the
+  // difference as in the march (exact comparisons for special centres).
+  auto far_mask = [&](int y, int z, float c) __attribute__((always_inline)) {
+    float v[14];
+#pragma unroll
+    for (int j = 0; j < 14; j++) {
+      const int dx = kOff3[j][0], dy = kOff3[j][1], dz = kOff3[j][2];
+      const __amdgpu_buffer_rsrc_t r = rsrc(plane_at(z + 2 * dz));
+      const int yy = min(max(y + 2 * dy, 0), my - 1);
+      v[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+          r, fxo[dx + 1], (int)((int64_t)yy * g.sy * 4), 0));
+    }
+    unsigned m = 0;
+#pragma unroll
+    for (int j = 13; j >= 0; j--)
+      m = push_sign(m, ((kPos3 >> j) & 1u) ? v[j] - c : c - v[j]);
+    if (wave_ballot(special_centre(c))) {
+      const float lo[4] = {v[0], v[1], v[2], v[3]};
+      const float md[6] = {v[4], v[5], v[6], v[7], v[8], v[9]};
+      const float hi[4] = {v[10], v[11], v[12], v[13]};
+      if (special_centre(c)) m = mask3(c, lo, md, hi) ^ kPos3;
+    }
+    return m;
+  };
   auto pmplane_at = [&](int z) {
     return pmb + (int64_t)(min(max(z, 0), mz - 1) >> 1) * pmplane;
   };
@@ -478,7 +496,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
           unsigned pm = 0;
           if (RP) pm = mid.pm[j >> 1];
           if (FAR && !RP && out_lane && !(x & 1))
-            pm = far_mask3(a.f, g, x, y, z, mid.v[j + 1]);
+            pm = far_mask(y, z, mid.v[j + 1]);
           bool d;
           if (IN) {
             d = mr[j] != pm;  // both are 14-bit masks
