@@ -180,7 +180,8 @@ void launch_needs(const Step *steps, int n, bool with_codes, int64_t *words,
 int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   const Step *steps, int n, uint8_t *codes, uint32_t *crit,
                   uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
-                  unsigned gen, bool final_group) {
+                  unsigned gen, bool final_group, int64_t *publish = nullptr,
+                  int publish_n = 0) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -265,6 +266,8 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   b.cap = cap;
   b.level_base = c->level_base;
   b.count_dev = count_dev;
+  b.publish = publish;
+  b.publish_n = publish_n;
   b.nan_flag = &c->flags[0];
   b.gen = gen;
   b.counts = c->counts;
@@ -445,7 +448,8 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
                         int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
                         uint32_t *crit, uint8_t *crit_codes, int64_t crit_capacity,
                         bool timed, pcrit_level_cb cb, void *user, int *kmax_out,
-                        int *group_end, unsigned *gen_out) {
+                        int *group_end, unsigned *gen_out,
+                        int64_t *publish = nullptr, bool *published = nullptr) {
   if (!c || !field || !codes || crit_capacity < 0 ||
       (crit_capacity > 0 && !crit))
     return PCRIT_E_ARG;
@@ -524,8 +528,12 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
   if (timed && hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
+    // the compaction of a last launch of one level publishes the offsets
+    const bool pub = publish && i + n > kmax && n == 1;
     st = enqueue_group(c, s, field, &steps[i], n, codes, crit, crit_codes,
-                       crit_capacity, nullptr, gen, i + n > kmax);
+                       crit_capacity, nullptr, gen, i + n > kmax,
+                       pub ? publish : nullptr, pub ? kmax + 2 : 0);
+    if (pub) *published = true;
     if (st) return st;
     if (timed && hipEventRecord(c->ev_level[i + n - 1], s) != hipSuccess)
       return PCRIT_E_HIP;
@@ -581,10 +589,12 @@ int pcrit_progressive_async(pcrit_ctx *c, void *hip_stream, const float *field,
   hipStream_t s = (hipStream_t)hip_stream;
   int kmax = 0, group_end[kMaxLevels];
   unsigned gen = 0;
+  bool published = false;
   int st = enqueue_progressive(c, s, field, nx, ny, nz, codes, crit, nullptr,
                                crit_capacity, false, nullptr, nullptr, &kmax,
-                               group_end, &gen);
+                               group_end, &gen, level_offsets_dev, &published);
   if (st) return st;
+  if (published) return PCRIT_OK;
   return launch_publish_offsets(c->level_base, kmax + 2, &c->flags[0], gen,
                                 level_offsets_dev, s) == hipSuccess
              ? PCRIT_OK

@@ -1159,8 +1159,14 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   if (chunk == a.nchunks - 1 && tid == 0) {
     const int64_t total = prefix + ctot;
     a.level_base[L.slot + 1] = base + total;
-    if (a.count_dev)
-      *a.count_dev = (*a.nan_flag == a.gen) ? -1 : total - lprefix;
+    const bool nan = *a.nan_flag == a.gen;
+    if (a.count_dev) *a.count_dev = nan ? -1 : total - lprefix;
+    // single-level launch: every other list offset was written by an
+    // earlier launch, the last one just above
+    if (a.publish) {
+      for (int i = 0; i + 1 < a.publish_n; i++) a.publish[i] = a.level_base[i];
+      a.publish[a.publish_n - 1] = nan ? -1 : base + total;
+    }
   }
 }
 

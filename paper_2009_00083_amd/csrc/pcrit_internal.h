@@ -134,6 +134,8 @@ struct CompactArgs {
   int64_t cap;
   int64_t *level_base;  // list offsets; [0] is 0
   int64_t *count_dev;   // may be null: total of the last level
+  int64_t *publish;     // may be null: level_base[0 .. publish_n) for the
+  int publish_n;        // caller (the last one -1 after a NaN sample)
   unsigned *nan_flag;
   unsigned gen;
   int *counts;          // per-chunk critical counts

@@ -355,8 +355,11 @@ def test_progressive_async_matches_sync(ctx, dev, shape):
     assert torch.equal(codes, p.codes)
 
 
-def test_progressive_async_nan_and_capacity(ctx, dev):
-    f = fieldgen.gaussian_field((20, 21, 66), 8, 5, noise=("uniform", 1e-3))
+@pytest.mark.parametrize("shape", [(20, 21, 66), (130, 130, 257)])
+def test_progressive_async_nan_and_capacity(ctx, dev, shape):
+    """Small grids publish the offsets with a kernel of their own, grids
+    whose level 0 has a launch of its own from the end of its compaction."""
+    f = fieldgen.gaussian_field(shape, 8, 5, noise=("uniform", 1e-3))
     ft = torch.from_numpy(f).to(dev)
     p = pc.progressive(ft, ctx=ctx)
     torch.cuda.synchronize()
