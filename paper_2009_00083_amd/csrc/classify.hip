@@ -1188,10 +1188,11 @@ hipError_t launch_tiles(const ClassifyArgs &a, hipStream_t st) {
 }
 
 // Tile depth along the marched axis: the deepest multiple of `step` (up to
-// `cap`) that still yields enough wave tiles to fill the GPU; small levels
-// get short tiles so that their march is short.
+// `cap`) that still yields 2048 wave tiles (two per SIMD); only small levels
+// get shorter tiles.  (Aiming at 8192 tiles made the fused coarse launch
+// 36 instead of 30 us: more waves than fit at once, each with a short march.)
 int tile_depth(int64_t columns, int n, int cap, int step) {
-  constexpr int64_t kWantTiles = 8192;
+  constexpr int64_t kWantTiles = 2048;
   int d = cap;
   while (d > step && columns * ((n + d - 1) / d) < kWantTiles) d -= step;
   return d;
