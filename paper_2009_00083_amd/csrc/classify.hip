@@ -417,8 +417,11 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
 
   // Classify the R vertices of plane z (parity `even`) in this lane's column;
   // their staged rows start at qb.
+  // Step of plane z: the bits from planes z-1 and z first, then the x-shifts
+  // of plane z+1 (its loads were issued one step earlier: waiting for them
+  // as late as possible), then the bits from plane z+1.
   auto step = [&](int z, bool even, int qb, const Plane3<R> &lo,
-                  const Plane3<R> &mid, const Plane3<R> &hi) {
+                  const Plane3<R> &mid, Plane3<R> &hi) {
     const bool zlive = z < z1;
     const bool z_inner = z > 0 && z < mz - 1;
     unsigned mr[R];
@@ -427,11 +430,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
       const int i = j + 1;
       const float c = mid.v[i];
       unsigned m;
-      m = push_sign(0u, hi.r[i] - c);              // 13 (1,1,1)
-      m = push_sign(m, hi.v[i + 1] - c);           // 12 (0,1,1)
-      m = push_sign(m, hi.r[i - 1] - c);           // 11 (1,0,1)
-      m = push_sign(m, hi.v[i] - c);               // 10 (0,0,1)
-      m = push_sign(m, mid.r[i] - c);              //  9 (1,1,0)
+      m = push_sign(0u, mid.r[i] - c);             //  9 (1,1,0)
       m = push_sign(m, c - mid.l[i - 1]);          //  8 (-1,-1,0)
       m = push_sign(m, mid.v[i + 1] - c);          //  7 (0,1,0)
       m = push_sign(m, c - mid.v[i - 1]);          //  6 (0,-1,0)
@@ -442,6 +441,18 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
       m = push_sign(m, c - lo.l[i]);               //  1 (-1,0,-1)
       m = push_sign(m, c - lo.v[i]);               //  0 (0,0,-1)
       mr[j] = m;
+    }
+    derive(hi);
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+      const int i = j + 1;
+      const float c = mid.v[i];
+      unsigned m;
+      m = push_sign(0u, hi.r[i] - c);              // 13 (1,1,1)
+      m = push_sign(m, hi.v[i + 1] - c);           // 12 (0,1,1)
+      m = push_sign(m, hi.r[i - 1] - c);           // 11 (1,0,1)
+      m = push_sign(m, hi.v[i] - c);               // 10 (0,0,1)
+      mr[j] |= m << 10;
     }
     // Rare: a centre whose differences may not carry the order.
     bool sp = false;
@@ -545,7 +556,6 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int z = zb + u;
-      derive(W[(u + 2) % U]);  // plane z+1
       load(pn, pmn, !(u & 1), W[(u + U - 1) % U]);
       if (zn < zlast) {
         pn += szb;
