@@ -520,7 +520,13 @@ def test_full_size(ctx, dev, name):
             d = gpu_classify(ctx, dev, f, k)
             assert_same(f, k, d, lref, f"{name} level {k}")
     log("reclassified per level", p.reclassified.tolist())
-    del r, p
+    # the asynchronous entry point (the bench's) enqueues the same work
+    codes_a, crit_a, offs_a = pc.progressive_async(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(offs_a.cpu().numpy(), p.offsets)
+    n = int(p.offsets[-1])
+    assert torch.equal(crit_a[:n], p.crit[:n]) and torch.equal(codes_a, p.codes)
+    del r, p, codes_a, crit_a
     # padded Morse count: with a +inf layer every original vertex is interior
     log("padded Morse count", name)
     pad = torch.nn.functional.pad(ft.unsqueeze(0), (1, 1, 1, 1) + ((1, 1) if f.ndim == 3 else ()),
