@@ -32,6 +32,7 @@ import numpy as np
 
 __all__ = [
     "CONFIGS", "gaussian_field", "config_field", "tie_field", "iid_field",
+    "device_iid_field",
 ]
 
 
@@ -170,3 +171,13 @@ def iid_field(shape, seed):
     """i.i.d. U[0,1) float32 samples."""
     rng = np.random.default_rng(seed)
     return rng.random(size=tuple(shape), dtype=np.float32)
+
+
+def device_iid_field(shape, seed, device):
+    """i.i.d. U[0,1) float32 samples drawn on ``device`` by torch's seeded
+    generator there (for grids too large to draw on the host).  Returns a
+    device tensor; tests copy the parts the oracle needs from it."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.rand(tuple(shape), generator=g, device=device, dtype=torch.float32)
