@@ -188,6 +188,39 @@ def test_special_values(ctx, dev):
     assert_same(f, 0, r, oracle.classify(f), "special values")
 
 
+def test_subnormal_values(ctx, dev):
+    """Subnormal samples (a smooth field decaying into the subnormal range,
+    mixed with exact ties and signed zeros): the sign of a difference of two
+    subnormals must still decide the order."""
+    rng = np.random.default_rng(5)
+    tiny = np.float32(1.4e-45)  # smallest positive subnormal
+    vals = np.array([0.0, -0.0, tiny, -tiny, 2 * tiny, 3e-40, -3e-40,
+                     1.1e-38, 1.2e-38], np.float32)
+    for shape in [(19, 21, 70), (67, 131)]:
+        f = vals[rng.integers(0, len(vals), size=shape)]
+        g = (rng.random(size=shape, dtype=np.float32) * np.float32(1e-39))
+        f = np.where(rng.random(size=shape) < 0.5, f, g).astype(np.float32)
+        assert (np.abs(f[f != 0]) < np.float32(1.18e-38)).any()
+        r = gpu_classify(ctx, dev, f)
+        assert_same(f, 0, r, oracle.classify(f), f"subnormal {shape}")
+        check_progressive(ctx, dev, f)
+
+
+def test_extreme_magnitudes(ctx, dev):
+    """Samples near +-FLT_MAX, whose differences overflow to +-inf (the sign
+    still carries the order), mixed with ordinary values and ties."""
+    rng = np.random.default_rng(6)
+    big = np.finfo(np.float32).max
+    vals = np.array([big, -big, np.nextafter(big, 0, dtype=np.float32),
+                     -np.nextafter(big, 0, dtype=np.float32), 1e38, -1e38,
+                     0.0, 1.0, -1.0], np.float32)
+    for shape in [(19, 21, 70), (67, 131)]:
+        f = vals[rng.integers(0, len(vals), size=shape)].astype(np.float32)
+        r = gpu_classify(ctx, dev, f)
+        assert_same(f, 0, r, oracle.classify(f), f"extreme {shape}")
+        check_progressive(ctx, dev, f)
+
+
 # ---------------------------------------------------------------------------
 # Progressive
 # ---------------------------------------------------------------------------
