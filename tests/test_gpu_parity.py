@@ -496,28 +496,8 @@ def test_bad_arguments(ctx, dev):
 
 
 # ---------------------------------------------------------------------------
-# Full-size workloads: sampled vertices and invariants
+# Full-size workloads: every vertex, and the padded Morse count
 # ---------------------------------------------------------------------------
-def _sampled_check(f, codes, level, n=20000, seed=0):
-    rng = np.random.default_rng(seed)
-    m = oracle.level_dims(f.shape, level)
-    xs = rng.integers(0, m[0], n)
-    ys = rng.integers(0, m[1], n)
-    zs = rng.integers(0, m[2], n)
-    # include the faces, edges and corners
-    corners = np.array(list(itertools.product(*[(0, mm - 1) for mm in m])))
-    xs = np.concatenate([xs, corners[:, 0]])
-    ys = np.concatenate([ys, corners[:, 1]])
-    zs = np.concatenate([zs, corners[:, 2]])
-    d = oracle.vertex_detail(f, np.stack([xs, ys, zs], 1), level)
-    s = 1 << level
-    if f.ndim == 3:
-        got = codes[zs * s, ys * s, xs * s]
-    else:
-        got = codes[ys * s, xs * s]
-    assert np.array_equal(got, d[:, 0].astype(np.uint8))
-
-
 def _morse_from_codes(codes_t, dim):
     h = torch.bincount(codes_t.reshape(-1).to(torch.int64), minlength=256).cpu().numpy()
     c = np.arange(256)
