@@ -213,9 +213,9 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     d.mz = (int)g.mz;
     d.rowwords = (int)g.rowwords;
     if (dim == 3)
-      plan_level3(d, fused || steps[0].mask_write >= 0);
+      plan_level3(d, fused || steps[0].mask_write >= 0, fused);
     else
-      plan_level2(d);
+      plan_level2(d, fused);
     d.tile_begin = tiles;
     tiles += d.ntiles;
     d.bits = c->bits + woff;

@@ -1198,31 +1198,39 @@ hipError_t launch_tiles(const ClassifyArgs &a, hipStream_t st) {
 }
 
 // Tile depth along the marched axis: the deepest multiple of `step` (up to
-// `cap`) that still yields 2048 wave tiles (two per SIMD); only small levels
-// get shorter tiles.  (Aiming at 8192 tiles made the fused coarse launch
-// 36 instead of 30 us: more waves than fit at once, each with a short march.)
-int tile_depth(int64_t columns, int n, int cap, int step) {
-  constexpr int64_t kWantTiles = 2048;
+// `cap`) that still yields `want` wave tiles; only levels too small for that
+// get shorter tiles.  Fused launches of small levels aim at 2048 tiles (two
+// per SIMD; aiming at 8192 made the fused coarse launch 36 instead of 30 us:
+// more waves than fit at once, each with a short march).  Single-level
+// launches aim at 8192 tiles, so that mid-size levels still spread over
+// most resident wave slots (measured at level 0 of the smooth 256^3 field:
+// 2048 tiles 47.6 us, 8192 tiles 39.9 us, 16384 45.0 us, 32768 61.8 us;
+// the 512^3 levels have more tiles than any of these at full depth).
+constexpr int64_t kWantTilesFused = 2048;
+constexpr int64_t kWantTilesLevel = 8192;
+int tile_depth(int64_t columns, int n, int cap, int step, int64_t want) {
   int d = cap;
-  while (d > step && columns * ((n + d - 1) / d) < kWantTiles) d -= step;
+  while (d > step && columns * ((n + d - 1) / d) < want) d -= step;
   return d;
 }
 
 }  // namespace
 
-void plan_level3(LevelDesc &l, bool write_masks) {
+void plan_level3(LevelDesc &l, bool write_masks, bool fused) {
   l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = (l.my + kTile3Y - 1) / kTile3Y;
-  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, zchunk_cap3(write_masks), kUnroll3);
+  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, zchunk_cap3(write_masks), kUnroll3,
+                        fused ? kWantTilesFused : kWantTilesLevel);
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor((uint32_t)l.nty, &l.nty_mul, &l.nty_shift);
 }
 
-void plan_level2(LevelDesc &l) {
+void plan_level2(LevelDesc &l, bool fused) {
   l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = 1;
-  l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2);
+  l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2,
+                        fused ? kWantTilesFused : kWantTilesLevel);
   l.ntiles = l.ntx * ((l.my + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor(1u, &l.nty_mul, &l.nty_shift);

@@ -143,8 +143,8 @@ struct CompactArgs {
 };
 
 // Fill the launch geometry of a level (tile depth, tile counts).
-void plan_level3(LevelDesc &l, bool write_masks);
-void plan_level2(LevelDesc &l);
+void plan_level3(LevelDesc &l, bool write_masks, bool fused);
+void plan_level2(LevelDesc &l, bool fused);
 
 // Division by an invariant d in [1, 2^31): with l = ceil(log2 d),
 // shift = 31 + l and mul = ceil(2^shift / d) (< 2^32), floor(n / d) equals
