@@ -220,6 +220,39 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def check_buffer(name, t, dtype, device, *, numel=None, min_numel=None):
+    """Reject a caller-supplied buffer that the library would write past or
+    misread: wrong type, wrong device, not contiguous, or too small.  Raises
+    PcritError(E_ARG) before anything is enqueued."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise PcritError(E_ARG, f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise PcritError(E_ARG, f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise PcritError(E_ARG, f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise PcritError(E_ARG, f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise PcritError(E_ARG, f"{name} must have {numel} elements, "
+                                f"got {t.numel()}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise PcritError(E_ARG, f"{name} must have at least {min_numel} "
+                                f"elements, got {t.numel()}")
+    return t
+
+
+def _capacity(capacity, crit, default):
+    """List capacity: as given, else the supplied list's length, else the
+    default (enough for every vertex)."""
+    if capacity is None:
+        capacity = crit.numel() if crit is not None else default
+    capacity = int(capacity)
+    if capacity < 0:
+        raise PcritError(E_ARG, "capacity must be >= 0")
+    return capacity
+
+
 @dataclass
 class ClassifyResult:
     codes: "object"           # uint8 tensor, full resolution
@@ -242,14 +275,18 @@ def classify(field, level: int = 0, *, ctx: Optional[Context] = None,
     nx, ny, nz = _check_field(field)
     lib = _load()
     c = _ctx_for(field, ctx)
+    m = level_dims(field.shape, level)
+    capacity = _capacity(capacity, crit, m[0] * m[1] * m[2])
     if codes is None:
         codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
-    if capacity is None:
-        m = level_dims(field.shape, level)
-        capacity = m[0] * m[1] * m[2]
+    check_buffer("codes", codes, torch.uint8, field.device, numel=field.numel())
     if crit is None:
         crit = torch.empty(max(capacity, 1), dtype=torch.int32,
                            device=field.device)
+    check_buffer("crit", crit, torch.int32, field.device, min_numel=capacity)
+    if count_dev is not None:
+        check_buffer("count_dev", count_dev, torch.int64, field.device,
+                     min_numel=1)
     cc = (torch.empty(max(capacity, 1), dtype=torch.uint8, device=field.device)
           if with_crit_codes else None)
     cnt = ctypes.c_int64(-1)
@@ -302,16 +339,20 @@ def progressive(field, *, ctx: Optional[Context] = None,
     lib = _load()
     c = _ctx_for(field, ctx)
     kmax, total = _hierarchy(tuple(field.shape))
-    if capacity is None:
-        capacity = total
+    capacity = _capacity(capacity, crit, total)
     if codes is None:
         codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
+    check_buffer("codes", codes, torch.uint8, field.device, numel=field.numel())
     if crit is None:
         crit = torch.empty(max(capacity, 1), dtype=torch.int32,
                            device=field.device)
+    check_buffer("crit", crit, torch.int32, field.device, min_numel=capacity)
     if with_crit_codes and crit_codes is None:
         crit_codes = torch.empty(max(capacity, 1), dtype=torch.uint8,
                                  device=field.device)
+    if crit_codes is not None:
+        check_buffer("crit_codes", crit_codes, torch.uint8, field.device,
+                     min_numel=capacity)
     offs = np.zeros(kmax + 2, np.int64)
     ms = np.zeros(kmax + 1, np.float32) if level_times else None
     rec = np.zeros(kmax + 1, np.int64)
@@ -340,14 +381,17 @@ def progressive_async(field, *, ctx: Optional[Context] = None,
     lib = _load()
     c = _ctx_for(field, ctx)
     kmax, total = _hierarchy(tuple(field.shape))
-    if capacity is None:
-        capacity = total
+    capacity = _capacity(capacity, crit, total)
     if codes is None:
         codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
+    check_buffer("codes", codes, torch.uint8, field.device, numel=field.numel())
     if crit is None:
         crit = torch.empty(max(capacity, 1), dtype=torch.int32, device=field.device)
+    check_buffer("crit", crit, torch.int32, field.device, min_numel=capacity)
     if offsets is None:
         offsets = torch.empty(kmax + 2, dtype=torch.int64, device=field.device)
+    check_buffer("offsets", offsets, torch.int64, field.device,
+                 min_numel=kmax + 2)
     _check(lib.pcrit_progressive_async(
         c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
         _ptr(codes), _ptr(crit), int(capacity), _ptr(offsets)),

@@ -11,7 +11,10 @@ SOURCES = ["csrc/classify.hip", "csrc/api.cpp", "csrc/link_table.cpp",
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-result", "-Wno-unused-value",
          # keep the compiler from forming packed fp32 instructions
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # f32 subnormals are kept, not flushed: the sign of a difference of
+         # two subnormal samples then carries their order exactly
+         "-fno-gpu-flush-denormals-to-zero"]
 
 
 def build(verbose: bool = False) -> str:

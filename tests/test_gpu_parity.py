@@ -495,6 +495,34 @@ def test_bad_arguments(ctx, dev):
     assert call(P(f), 6, 5, 4, 0, P(codes), P(crit), 200) == 0
 
 
+def test_binding_rejects_bad_buffers_on_device(ctx, dev):
+    """Undersized or mistyped output buffers raise before any launch."""
+    f = torch.zeros((6, 7, 8), dtype=torch.float32, device=dev)
+    n = f.numel()
+    cases = [
+        dict(codes=torch.zeros(n - 1, dtype=torch.uint8, device=dev)),
+        dict(codes=torch.zeros(n, dtype=torch.int32, device=dev)),
+        dict(crit=torch.zeros(n - 1, dtype=torch.int32, device=dev), capacity=n),
+        dict(crit=torch.zeros(n, dtype=torch.int64, device=dev)),
+        dict(codes=torch.zeros(f.shape, dtype=torch.uint8)),
+    ]
+    for kw in cases:
+        with pytest.raises(pc.PcritError) as e:
+            pc.classify(f, ctx=ctx, **kw)
+        assert e.value.status == pc.E_ARG
+    with pytest.raises(pc.PcritError):
+        pc.progressive(f, ctx=ctx, crit_codes=torch.zeros(3, dtype=torch.uint8, device=dev),
+                       capacity=10)
+    with pytest.raises(pc.PcritError):
+        pc.progressive_async(f, ctx=ctx, offsets=torch.zeros(2, dtype=torch.int64, device=dev))
+    # a short list without a capacity gets the list's length as capacity
+    crit = torch.zeros(5, dtype=torch.int32, device=dev)
+    g = torch.from_numpy(fieldgen.iid_field((6, 7, 8), 3)).to(dev)
+    r = pc.classify(g, ctx=ctx, crit=crit)
+    torch.cuda.synchronize()
+    assert r.status == pc.E_CAPACITY and r.count > 5 and r.crit.numel() == 5
+
+
 # ---------------------------------------------------------------------------
 # Full-size workloads: every vertex, and the padded Morse count
 # ---------------------------------------------------------------------------

@@ -158,3 +158,32 @@ def test_preview_f1_matches_bruteforce(seed):
     f1b, mb = _greedy_f1(shape, level, p, pcd, e, ec)
     assert m == mb
     assert f1 == pytest.approx(f1b)
+
+
+def test_binding_rejects_bad_buffers():
+    """Caller-supplied buffers are checked before any call into the library:
+    wrong dtype, device, layout or size raises PcritError(E_ARG)."""
+    import torch
+    cpu = torch.device("cpu")
+    chk = pc.binding.check_buffer
+    good = torch.zeros(10, dtype=torch.int32)
+    assert chk("crit", good, torch.int32, cpu, min_numel=10) is good
+    bad = [
+        (torch.zeros(10, dtype=torch.int64), dict(min_numel=10)),   # dtype
+        (torch.zeros(9, dtype=torch.int32), dict(min_numel=10)),    # too small
+        (torch.zeros(20, dtype=torch.int32)[::2], dict(min_numel=10)),  # strided
+        (torch.zeros(11, dtype=torch.int32), dict(numel=10)),       # exact size
+        (np.zeros(10, np.int32), dict(min_numel=10)),              # not a tensor
+    ]
+    for t, kw in bad:
+        with pytest.raises(pc.PcritError) as e:
+            chk("crit", t, torch.int32, cpu, **kw)
+        assert e.value.status == pc.E_ARG
+    with pytest.raises(pc.PcritError):
+        chk("crit", good, torch.int32, torch.device("cuda:0"), min_numel=1)
+    # capacity defaults to the supplied list's length, never beyond it
+    assert pc.binding._capacity(None, good, 1000) == 10
+    assert pc.binding._capacity(None, None, 1000) == 1000
+    assert pc.binding._capacity(7, good, 1000) == 7
+    with pytest.raises(pc.PcritError):
+        pc.binding._capacity(-1, None, 1000)

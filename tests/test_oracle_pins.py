@@ -364,6 +364,86 @@ def test_level_equals_subsampled_grid(oracle_mod, shape):
             a.codes[tuple(slice(0, None, s) for _ in shape)], b.codes)
 
 
+def _window_planes(shape, level, a, b):
+    """Full-resolution slow-axis positions of level-local planes [a, b)."""
+    return np.arange(a, b) * (1 << level)
+
+
+@pytest.mark.parametrize("shape", [(19, 14, 11), (13, 9, 20), (37, 23), (21, 40)])
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_slow_range_window_equals_full_run(oracle_mod, shape, level):
+    """Classification is local to a vertex's star (Section 3.1), so the
+    windowed mode (level-local planes / rows [a, b) of the slowest axis) must
+    give exactly the codes and list entries of the full-range run inside the
+    window: windows at the low boundary, in the interior and at the high
+    boundary."""
+    f = fieldgen.tie_field(shape, 3 + level, 5)
+    full = oracle_mod.classify(f, level=level)
+    assert full.status == 0
+    m = oracle_mod.level_dims(shape, level)
+    n_slow = m[2] if len(shape) == 3 else m[1]
+    s = 1 << level
+    plane = int(np.prod(shape[1:]))  # full-resolution samples per slow step
+    for a, b in [(0, 2), (1, n_slow - 1), (n_slow // 2, n_slow // 2 + 1),
+                 (n_slow - 2, n_slow), (0, n_slow)]:
+        w = oracle_mod.classify(f, level=level, slow_range=(a, b))
+        assert w.status == 0
+        # codes: every level position inside the window, none outside
+        sel = [slice(0, None, s)] * len(shape)
+        sel[0] = _window_planes(shape, level, a, b)
+        assert np.array_equal(w.codes[tuple(sel)], full.codes[tuple(sel)])
+        outside = np.ones(shape[0], bool)
+        outside[_window_planes(shape, level, a, b)] = False
+        assert not w.codes[outside].any()
+        lo, hi = a * s * plane, (b - 1) * s * plane + plane
+        inside = full.crit[(full.crit >= lo) & (full.crit < hi)]
+        assert np.array_equal(w.crit, inside)
+        assert w.count == len(inside)
+
+
+@pytest.mark.parametrize("shape", [(17, 12, 9), (23, 15), (40, 7, 6)])
+def test_window_of_sub_array_with_neighbour_planes(oracle_mod, shape):
+    """The form the largest-grid GPU test uses: planes (rows) [a, b) are
+    classified from the sub-array [a-1, b+1) clipped to the grid, and its
+    indices, shifted by (a-1) planes, are the full run's.  Every window vertex
+    keeps its whole star (one plane per side), and shifting all indices by a
+    constant keeps their order."""
+    f = fieldgen.iid_field(shape, 11)
+    f[::3] = np.round(f[::3] * 4) / 4  # ties across planes
+    full = oracle_mod.classify(f)
+    n0 = shape[0]
+    plane = int(np.prod(shape[1:]))
+    for a, b in [(0, 3), (4, 9), (n0 - 3, n0), (0, n0), (1, 2)]:
+        lo, hi = max(a - 1, 0), min(b + 1, n0)
+        sub = np.ascontiguousarray(f[lo:hi])
+        w = oracle_mod.classify(sub, slow_range=(a - lo, b - lo))
+        assert w.status == 0
+        assert np.array_equal(w.codes[a - lo:b - lo], full.codes[a:b])
+        got = w.crit.astype(np.int64) + lo * plane
+        exp = full.crit[(full.crit >= a * plane) & (full.crit < b * plane)]
+        assert np.array_equal(got, exp.astype(np.int64))
+
+
+def test_window_matches_bruteforce(oracle_mod):
+    """Windowed classification of a tiny tie-heavy grid against the
+    independent brute force (GF(2) Betti numbers of both link parts), vertex
+    by vertex: a vertex is regular iff both parts have b0 = 1 and b1 = 0."""
+    shape = (5, 4, 3)
+    f = fieldgen.tie_field(shape, 9, 3)
+    fx, sxyz = bf.field_xyz(f)
+    cplx = bf.Complex(sxyz)
+    for a, b in [(0, 1), (2, 4), (4, 5)]:
+        w = oracle_mod.classify(f, slow_range=(a, b))
+        for z in range(a, b):
+            for y in range(shape[1]):
+                for x in range(shape[2]):
+                    bl = bf.link_part_betti(cplx, fx, (x, y, z), True)
+                    bu = bf.link_part_betti(cplx, fx, (x, y, z), False)
+                    regular = bl[:2] == (1, 0) and bu[:2] == (1, 0)
+                    got = bool(oracle_mod.is_critical_code(w.codes[z, y, x]))
+                    assert got == (not regular), (x, y, z)
+
+
 def test_level_dims_and_max_level(oracle_mod):
     assert oracle_mod.level_dims((512, 512, 512), 8) == (2, 2, 2)
     assert oracle_mod.level_dims((512, 512, 512), 0) == (512, 512, 512)
