@@ -67,6 +67,11 @@ extern "C" {
 #define PCRIT_E_NAN (-5)      /* a sample of the level is NaN */
 #define PCRIT_E_HIP (-6)      /* a HIP runtime call failed */
 #define PCRIT_E_OOM (-7)      /* device allocation of scratch failed */
+#define PCRIT_E_SCRATCH (-8)  /* level too large for the fixed scratch of
+                                 pcrit_classify_noalloc */
+
+/* Size in bytes of the fixed per-GPU scratch of pcrit_classify_noalloc. */
+#define PCRIT_NOALLOC_SCRATCH_BYTES (32ll << 20)
 
 typedef struct pcrit_ctx pcrit_ctx;
 
@@ -129,6 +134,28 @@ int pcrit_classify(pcrit_ctx *ctx, void *hip_stream, const float *field,
                    uint8_t *codes, uint32_t *crit, uint8_t *crit_codes,
                    int64_t crit_capacity, int64_t *crit_count_host,
                    int64_t *crit_count_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * classification as pcrit_classify, with the same arguments, results and
+ * errors, but the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  Its scratch (the level's critical bitmask,
+ * one 64-bit word per 64 columns of each level row, then 4 bytes per
+ * compaction chunk) lives in a fixed device array of
+ * PCRIT_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; its
+ * device address is looked up by pcrit_create.  A level whose scratch does
+ * not fit (about 2^28 vertices with rows of a multiple of 64 columns) is
+ * rejected with PCRIT_E_SCRATCH before anything is enqueued.  Every call on
+ * one GPU shares that GPU's array, whatever its context or stream: calls
+ * that overlap in time on one GPU race and must be serialised by the
+ * caller.  Nothing in the array needs clearing between calls (every word a
+ * call reads, it has written first).  Kernel timing
+ * (pcrit_set_kernel_timing) is not recorded by this call. */
+int pcrit_classify_noalloc(pcrit_ctx *ctx, void *hip_stream, const float *field,
+                           int64_t nx, int64_t ny, int64_t nz, int level,
+                           uint8_t *codes, uint32_t *crit, uint8_t *crit_codes,
+                           int64_t crit_capacity, int64_t *crit_count_host,
+                           int64_t *crit_count_dev);
 
 /* Called after a level of pcrit_progressive completed (the stream is
  * synchronised first): level, number of critical vertices of that level. */

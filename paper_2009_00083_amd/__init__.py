@@ -8,7 +8,8 @@ streams.  There is no CPU fallback: if the library is missing, every call
 raises.
 """
 from .binding import (  # noqa: F401
-    PcritError, Context, classify, progressive, progressive_async, max_level, level_dims,
+    PcritError, Context, classify, classify_noalloc, progressive, progressive_async, max_level, level_dims,
     link_table, preview_f1, library_path, decode, is_critical, point_type,
-    E_ARG, E_DIMS, E_LEVEL, E_CAPACITY, E_NAN, E_HIP, E_OOM,
+    E_ARG, E_DIMS, E_LEVEL, E_CAPACITY, E_NAN, E_HIP, E_OOM, E_SCRATCH,
+    NOALLOC_SCRATCH_BYTES,
 )

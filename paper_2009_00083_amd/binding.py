@@ -17,6 +17,8 @@ from typing import List, Optional
 import numpy as np
 
 E_ARG, E_DIMS, E_LEVEL, E_CAPACITY, E_NAN, E_HIP, E_OOM = -1, -2, -3, -4, -5, -6, -7
+E_SCRATCH = -8
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpcrit.so")
@@ -24,7 +26,8 @@ _lib = None
 
 EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_max_level", "pcrit_level_dims", "pcrit_link_table",
-            "pcrit_classify", "pcrit_progressive", "pcrit_progressive_async",
+            "pcrit_classify", "pcrit_classify_noalloc", "pcrit_progressive",
+            "pcrit_progressive_async",
             "pcrit_set_kernel_timing", "pcrit_kernel_ms", "pcrit_preview_f1")
 
 
@@ -64,6 +67,8 @@ def _load():
     lib.pcrit_classify.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp, vp, vp,
                                    i64, p64, vp]
     lib.pcrit_classify.restype = i32
+    lib.pcrit_classify_noalloc.argtypes = lib.pcrit_classify.argtypes
+    lib.pcrit_classify_noalloc.restype = i32
     lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
     lib.NULL_CB = ctypes.cast(None, lib.LEVEL_CB)
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
@@ -302,6 +307,41 @@ def classify(field, level: int = 0, *, ctx: Optional[Context] = None,
     k = max(0, min(n, capacity))
     return ClassifyResult(codes, crit[:k], None if cc is None else cc[:k], n,
                           st)
+
+
+def classify_noalloc(field, level: int, codes, crit, *, ctx: Context,
+                     crit_codes=None, count_dev=None, stream=None,
+                     check: bool = True) -> ClassifyResult:
+    """pcrit_classify_noalloc: the direct pass with the library's fixed
+    per-GPU scratch; the caller supplies every buffer (codes, crit, and
+    optionally crit_codes and count_dev), so nothing is allocated here or in
+    the library.  The capacity is the length of ``crit``.  Without
+    ``count_dev`` the call synchronises and returns the count."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    lib = _load()
+    check_buffer("codes", codes, torch.uint8, field.device, numel=field.numel())
+    check_buffer("crit", crit, torch.int32, field.device)
+    capacity = crit.numel()
+    if crit_codes is not None:
+        check_buffer("crit_codes", crit_codes, torch.uint8, field.device,
+                     min_numel=capacity)
+    if count_dev is not None:
+        check_buffer("count_dev", count_dev, torch.int64, field.device,
+                     min_numel=1)
+    cnt = ctypes.c_int64(-1)
+    st = lib.pcrit_classify_noalloc(
+        ctx.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
+        int(level), _ptr(codes), _ptr(crit), _ptr(crit_codes), int(capacity),
+        None if count_dev is not None else ctypes.byref(cnt), _ptr(count_dev))
+    if check and st not in (0, E_CAPACITY):
+        raise PcritError(st, "pcrit_classify_noalloc")
+    if count_dev is not None:
+        return ClassifyResult(codes, crit, crit_codes, -1, st)
+    n = cnt.value
+    k = max(0, min(n, capacity))
+    return ClassifyResult(codes, crit[:k],
+                          None if crit_codes is None else crit_codes[:k], n, st)
 
 
 @dataclass

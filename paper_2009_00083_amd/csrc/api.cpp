@@ -12,6 +12,9 @@
 
 using namespace pcrit;
 
+static_assert(kNoAllocScratchBytes == PCRIT_NOALLOC_SCRATCH_BYTES,
+              "scratch size of the header and of the library");
+
 namespace {
 
 constexpr int kMaxLevels = 40;
@@ -177,11 +180,13 @@ void launch_needs(const Step *steps, int n, bool with_codes, int64_t *words,
 // level's masks computed from the field, only the finest level stores its
 // codes at full resolution (its vertices include those of the others), and
 // the others keep dense level codes for crit_codes.
+// `bits` and `counts` are the launch's scratch (the context's, or the fixed
+// array of the allocation-free entry point).
 int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   const Step *steps, int n, uint8_t *codes, uint32_t *crit,
                   uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
-                  unsigned gen, bool final_group, int64_t *publish = nullptr,
-                  int publish_n = 0) {
+                  unsigned gen, bool final_group, uint64_t *bits, int *counts,
+                  int64_t *publish = nullptr, int publish_n = 0) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -218,7 +223,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
       plan_level2(d, fused);
     d.tile_begin = tiles;
     tiles += d.ntiles;
-    d.bits = c->bits + woff;
+    d.bits = bits + woff;
     d.lcodes = fused && !last && crit_codes ? c->lcodes + loff : nullptr;
     if (!fused && sp.mask_read >= 0) d.prev_masks = c->masks[sp.mask_read];
     if (sp.prev) {
@@ -270,7 +275,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   b.publish_n = publish_n;
   b.nan_flag = &c->flags[0];
   b.gen = gen;
-  b.counts = c->counts;
+  b.counts = counts;
   b.reclass_acc = c->reclass_acc;
   record_kernel(c, 1, tlevel, 0, st);
   if (launch_compact(b, small, st) != hipSuccess) return PCRIT_E_HIP;
@@ -297,6 +302,8 @@ const char *pcrit_strerror(int status) {
     case PCRIT_E_NAN: return "NaN sample in the field";
     case PCRIT_E_HIP: return "HIP runtime error";
     case PCRIT_E_OOM: return "device allocation failed";
+    case PCRIT_E_SCRATCH:
+      return "level too large for the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -342,6 +349,8 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
       hip_device >= ndev)
     return PCRIT_E_HIP;
   if (hipSetDevice(hip_device) != hipSuccess) return PCRIT_E_HIP;
+  // device address of this GPU's fixed scratch (pcrit_classify_noalloc)
+  if (noalloc_scratch_init(hip_device) != hipSuccess) return PCRIT_E_HIP;
   pcrit_ctx *c = new pcrit_ctx();
   c->device = hip_device;
   // device tables are indexed by raw masks (true mask ^ kPos)
@@ -427,7 +436,53 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
   st = enqueue_group(c, s, field, &step, 1, codes, crit, crit_codes,
-                     crit_capacity, crit_count_dev, gen, true);
+                     crit_capacity, crit_count_dev, gen, true, c->bits, c->counts);
+  if (st) return st;
+  if (!crit_count_host) return PCRIT_OK;
+  if (read_status(c, s)) return PCRIT_E_HIP;
+  const int64_t count = c->h_base[1] - c->h_base[0];
+  *crit_count_host = count;
+  if (c->h_flags[0] == gen) return PCRIT_E_NAN;
+  return count > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
+}
+
+int pcrit_classify_noalloc(pcrit_ctx *c, void *hip_stream, const float *field,
+                           int64_t nx, int64_t ny, int64_t nz, int level,
+                           uint8_t *codes, uint32_t *crit, uint8_t *crit_codes,
+                           int64_t crit_capacity, int64_t *crit_count_host,
+                           int64_t *crit_count_dev) {
+  if (!c || !field || !codes || crit_capacity < 0 ||
+      (crit_capacity > 0 && !crit))
+    return PCRIT_E_ARG;
+  if (misaligned(field, 4) || (crit && misaligned(crit, 4)) ||
+      (crit_count_dev && misaligned(crit_count_dev, 8)))
+    return PCRIT_E_ARG;
+  Geom g;
+  int st = make_geom(nx, ny, nz, level, &g);
+  if (st) return st;
+  Step step;
+  step.g = g;
+  int64_t words, chunks, lbytes;
+  launch_needs(&step, 1, crit_codes != nullptr, &words, &chunks, &lbytes);
+  // bitmask words, then the chunk counts at a 256-byte boundary
+  const int64_t counts_at = (words * 8 + 255) / 256 * 256;
+  if (counts_at + chunks * (int64_t)sizeof(int) > kNoAllocScratchBytes)
+    return PCRIT_E_SCRATCH;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  char *base = static_cast<char *>(noalloc_scratch(c->device));
+  if (!base) return PCRIT_E_HIP;
+  // Nothing in the scratch has to start at zero: the classification writes
+  // every bitmask word of the level and the count kernel every chunk count
+  // before they are read.  Kernel timing is not recorded here.
+  const uint64_t timing = c->timing;
+  c->timing = 0;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const unsigned gen = next_gen(c);
+  reset_kernel_marks(c);
+  st = enqueue_group(c, s, field, &step, 1, codes, crit, crit_codes, crit_capacity,
+                     crit_count_dev, gen, true, reinterpret_cast<uint64_t *>(base),
+                     reinterpret_cast<int *>(base + counts_at));
+  c->timing = timing;
   if (st) return st;
   if (!crit_count_host) return PCRIT_OK;
   if (read_status(c, s)) return PCRIT_E_HIP;
@@ -531,7 +586,7 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
     // the compaction of a last launch of one level publishes the offsets
     const bool pub = publish && i + n > kmax && n == 1;
     st = enqueue_group(c, s, field, &steps[i], n, codes, crit, crit_codes,
-                       crit_capacity, nullptr, gen, i + n > kmax,
+                       crit_capacity, nullptr, gen, i + n > kmax, c->bits, c->counts,
                        pub ? publish : nullptr, pub ? kmax + 2 : 0);
     if (pub) *published = true;
     if (st) return st;

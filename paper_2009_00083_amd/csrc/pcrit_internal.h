@@ -174,4 +174,10 @@ hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
                            bool write_masks, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st);
 
+// Fixed scratch of the allocation-free entry point (one copy per GPU):
+// critical bitmask words, then per-chunk counts at a 256-byte boundary.
+constexpr int64_t kNoAllocScratchBytes = int64_t(32) << 20;
+hipError_t noalloc_scratch_init(int device);  // with `device` current
+void *noalloc_scratch(int device);            // null before the init
+
 }  // namespace pcrit
