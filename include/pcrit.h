@@ -161,15 +161,17 @@ int pcrit_classify_noalloc(pcrit_ctx *ctx, void *hip_stream, const float *field,
  * synchronised first): level, number of critical vertices of that level. */
 typedef void (*pcrit_level_cb)(int level, int64_t count, void *user);
 
-/* Progressive classification: levels k_max, k_max-1, ..., 0 in turn.
- * Level k_max is classified directly.  At every finer level each new vertex
- * (a midpoint inserted by the subdivision) is classified, while a vertex
- * already present at level k+1 is re-classified only if its polarity mask
- * or its set of absent (off-grid) neighbours changed, i.e. if some new
+/* Progressive classification: levels k_max, k_max-1, ..., 0 in turn, each
+ * level's list complete before the next level starts.  A vertex already
+ * present at level k+1 needs re-classifying at level k only if its polarity
+ * mask or its set of absent (off-grid) neighbours changed, i.e. if some new
  * neighbour (the midpoint of its level-(k+1) edge) lies on the other side of
- * it than that edge's far end; an unchanged vertex keeps its code and its
- * critical status, which is exact because the code is a function of the
- * mask and the absent set only.
+ * it than that edge's far end; otherwise its code and critical status are
+ * unchanged, because the code is a function of the mask and the absent set
+ * only.  The kernels classify every vertex of every level (an old vertex's
+ * code read again equals the kept one, and its row is classified anyway
+ * for the new vertices around it); on request they also count the old
+ * vertices that changed (reclassified_host).
  *   codes         device, nx*ny*nz bytes; ends holding the level-0 code of
  *                 every vertex (stored by the level-0 pass; coarser levels
  *                 store theirs there only when crit_codes is set)
@@ -185,7 +187,11 @@ typedef void (*pcrit_level_cb)(int level, int64_t count, void *user);
  *                 events).  Levels whose work shares one launch (see below)
  *                 report the same time
  *   reclassified_host  host, k_max+1 entries or NULL: number of old vertices
- *                 re-classified at each level (index i; 0 for level k_max)
+ *                 whose polarity mask or absent set changed at each level
+ *                 (index i; 0 for level k_max).  Non-NULL makes the call
+ *                 test every old vertex against the previous level's
+ *                 polarity masks (stored between launches), which costs
+ *                 memory traffic; NULL skips the test
  *   cb, user      optional per-level callback (forces a synchronisation per
  *                 level)
  * Levels of at most 2^22 vertices are latency bound: unless cb is set, the

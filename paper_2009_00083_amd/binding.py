@@ -352,7 +352,7 @@ class ProgressiveResult:
     levels: List[int]           # k_max .. 0
     offsets: np.ndarray         # k_max + 2 entries
     level_ms: Optional[np.ndarray]  # ms to each level's completion, or None
-    reclassified: np.ndarray    # old vertices re-classified per level
+    reclassified: Optional[np.ndarray]  # old vertices re-classified per level
     status: int
 
     def level_list(self, level: int):
@@ -368,12 +368,17 @@ def progressive(field, *, ctx: Optional[Context] = None,
                 capacity: Optional[int] = None, with_crit_codes: bool = False,
                 codes=None, crit=None, crit_codes=None, stream=None,
                 callback=None, level_times: bool = False,
+                count_reclassified: bool = False,
                 check: bool = True) -> ProgressiveResult:
     """Coarse-to-fine classification over every level of the hierarchy.
 
     With ``level_times`` the result carries the stream time from the first
     kernel to each level's completion (level_ms); without, no events are
-    recorded and level_ms is None."""
+    recorded and level_ms is None.  With ``count_reclassified`` the result
+    carries, per level, the number of old vertices whose polarity mask or
+    absent set changed (``reclassified``; the library then tests every old
+    vertex against the previous level); otherwise ``reclassified`` is
+    None."""
     import torch
     nx, ny, nz = _check_field(field)
     lib = _load()
@@ -395,13 +400,13 @@ def progressive(field, *, ctx: Optional[Context] = None,
                      min_numel=capacity)
     offs = np.zeros(kmax + 2, np.int64)
     ms = np.zeros(kmax + 1, np.float32) if level_times else None
-    rec = np.zeros(kmax + 1, np.int64)
+    rec = np.zeros(kmax + 1, np.int64) if count_reclassified else None
     cb = lib.LEVEL_CB(callback) if callback else lib.NULL_CB
     st = lib.pcrit_progressive(
         c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz,
         _ptr(codes), _ptr(crit), _ptr(crit_codes), int(capacity),
         offs.ctypes.data, None if ms is None else ms.ctypes.data,
-        rec.ctypes.data, cb, None)
+        None if rec is None else rec.ctypes.data, cb, None)
     if check and st not in (0, E_CAPACITY):
         raise PcritError(st, "pcrit_progressive")
     return ProgressiveResult(codes, crit, crit_codes,

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "../../include/pcrit.h"
 #include "pcrit_internal.h"
@@ -26,7 +27,10 @@ struct Geom {
   int64_t s = 1;
   int64_t mx = 0, my = 0, mz = 0;
   int64_t rowwords = 0, rows = 0, words = 0;
+  bool quad = false;  // classified on quad tiles
 };
+
+void set_quad(Geom *g, bool quad) { g->quad = quad; }
 
 int check_dims(int64_t nx, int64_t ny, int64_t nz) {
   if (nx < 2 || ny < 2 || nz < 1) return PCRIT_E_DIMS;
@@ -76,6 +80,7 @@ bool misaligned(const void *p, size_t a) {
 struct pcrit_ctx {
   int device = 0;
   uint8_t *lut3 = nullptr, *lut2 = nullptr;
+  uint8_t *lutq = nullptr;  // quad-tile tables (kQuadTableBytes bytes)
   uint64_t *bits = nullptr;  // critical bitmasks of the levels of one launch
   int64_t bits_words = 0;
   int *counts = nullptr;  // per-chunk critical counts of the compaction
@@ -248,18 +253,34 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     q.chunk_begin = (int)chunks;
     q.lcodes = d.lcodes;
     q.reclass_out = sp.reclass_out;
-    q.linear = g.s == 1 && g.mx == g.rowwords * kTileCols;
+    q.linear = g.s == 1 && g.mx == g.rowwords * 64;
     woff += g.words;
     if (d.lcodes) loff += level_vertices(g);
     chunks += (g.words + cw - 1) / cw;
   }
   a.ntiles = tiles;
   const int tlevel = steps[n - 1].g.level;  // a launch is timed as its finest level
-  record_kernel(c, 0, tlevel, 0, st);
   const Step &s0 = steps[0];
-  if (launch_classify(a, dim, !fused && s0.mask_read >= 0,
-                      !fused && s0.mask_write >= 0, st) != hipSuccess)
+  // Full-resolution and stride-2 levels of 3D grids with 16-byte aligned
+  // rows take the quad tiles, unless the launch stores or reads masks for
+  // the re-classification count.
+  const bool quad = !fused && s0.g.quad;
+  record_kernel(c, 0, tlevel, 0, st);
+  if (quad) {
+    QuadArgs q{};
+    q.f = field;
+    q.fbytes = s0.g.nx * s0.g.ny * s0.g.nz * (int64_t)sizeof(float);
+    q.codes = a.lv[0].write_codes ? codes : nullptr;
+    q.lut = c->lutq;
+    q.lv = a.lv[0];
+    plan_level_quad(q.lv);
+    q.nan_flag = a.nan_flag;
+    q.gen = gen;
+    if (launch_classify_quad(q, st) != hipSuccess) return PCRIT_E_HIP;
+  } else if (launch_classify(a, dim, !fused && s0.mask_read >= 0,
+                             !fused && s0.mask_write >= 0, st) != hipSuccess) {
     return PCRIT_E_HIP;
+  }
   record_kernel(c, 0, tlevel, 1, st);
 
   b.nchunks = (int)chunks;
@@ -355,12 +376,15 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   c->device = hip_device;
   // device tables are indexed by raw masks (true mask ^ kPos)
   uint8_t t3[kLut3Size], t2[kLut2Size], h3[kLut3Size], h2[kLut2Size];
+  std::vector<uint8_t> hq(kQuadTableBytes);
   build_link_table3(t3);
   build_link_table2(t2);
   for (int i = 0; i < kLut3Size; i++) h3[i] = t3[i ^ kPos3];
   for (int i = 0; i < kLut2Size; i++) h2[i] = t2[i ^ kPos2];
+  build_quad_table3(t3, hq.data());
   bool ok = hipMalloc(&c->lut3, kLut3Size) == hipSuccess &&
             hipMalloc(&c->lut2, kLut2Size) == hipSuccess &&
+            hipMalloc(&c->lutq, kQuadTableBytes) == hipSuccess &&
             hipMalloc(&c->status, kStatusBytes) == hipSuccess &&
             hipMalloc(&c->reclass_acc, kMaxFused * sizeof(unsigned)) == hipSuccess &&
             hipHostMalloc(&c->h_status, kStatusBytes) == hipSuccess;
@@ -372,6 +396,7 @@ int pcrit_create(pcrit_ctx **out, int hip_device) {
   }
   ok = ok && hipMemcpy(c->lut3, h3, kLut3Size, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(c->lut2, h2, kLut2Size, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(c->lutq, hq.data(), kQuadTableBytes, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemset(c->status, 0, kStatusBytes) == hipSuccess &&
        hipMemset(c->reclass_acc, 0, kMaxFused * sizeof(unsigned)) == hipSuccess;
   ok = ok && hipEventCreate(&c->ev_start) == hipSuccess;
@@ -392,6 +417,7 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipDeviceSynchronize();
   hipFree(c->lut3);
   hipFree(c->lut2);
+  hipFree(c->lutq);
   hipFree(c->bits);
   hipFree(c->counts);
   hipFree(c->lcodes);
@@ -424,6 +450,7 @@ int pcrit_classify(pcrit_ctx *c, void *hip_stream, const float *field,
   Geom g;
   int st = make_geom(nx, ny, nz, level, &g);
   if (st) return st;
+  set_quad(&g, quad_eligible(field, nx, g.s, g.dim));
   if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
   hipStream_t s = (hipStream_t)hip_stream;
   Step step;
@@ -460,6 +487,7 @@ int pcrit_classify_noalloc(pcrit_ctx *c, void *hip_stream, const float *field,
   Geom g;
   int st = make_geom(nx, ny, nz, level, &g);
   if (st) return st;
+  set_quad(&g, quad_eligible(field, nx, g.s, g.dim));
   Step step;
   step.g = g;
   int64_t words, chunks, lbytes;
@@ -499,11 +527,13 @@ namespace {
 // Plans and enqueues a progressive call (levels k_max .. 0) on `s`: level
 // steps, their grouping into launches, scratch sizing, then the launches.
 // With a callback every level completes (and is reported) on its own.
+// With `count` every old vertex is tested against the previous level (its
+// stored or recomputed polarity mask) and the re-classified ones counted.
 int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
                         int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
                         uint32_t *crit, uint8_t *crit_codes, int64_t crit_capacity,
-                        bool timed, pcrit_level_cb cb, void *user, int *kmax_out,
-                        int *group_end, unsigned *gen_out,
+                        bool timed, bool count, pcrit_level_cb cb, void *user,
+                        int *kmax_out, int *group_end, unsigned *gen_out,
                         int64_t *publish = nullptr, bool *published = nullptr) {
   if (!c || !field || !codes || crit_capacity < 0 ||
       (crit_capacity > 0 && !crit))
@@ -530,7 +560,7 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
     Step &sp = steps[i];
     sp.g = geo[k];
     sp.slot = i;
-    if (i > 0) {
+    if (i > 0 && count) {
       sp.prev = &geo[k + 1];
       sp.dirty = true;
       sp.mask_read = (i - 1) & 1;
@@ -543,8 +573,11 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
       while (j <= kmax && j - i < kMaxFused && level_vertices(steps[j].g) <= kSmallLevel)
         j++;
     group_end[i] = j;
-    // the last level of a launch stores its masks for the next launch
-    if (j <= kmax) steps[j - 1].mask_write = (j - 1) & 1;
+    // counting: the last level of a launch stores its masks for the next
+    // launch; otherwise a level of its own may take the quad tiles
+    if (count && j <= kmax) steps[j - 1].mask_write = (j - 1) & 1;
+    if (!count && j == i + 1)
+      set_quad(&steps[i].g, quad_eligible(field, nx, steps[i].g.s, steps[i].g.dim));
     i = j;
   }
   int64_t need_words = 0, need_chunks = 0, need_l = 0, need_masks = 0;
@@ -615,8 +648,10 @@ int pcrit_progressive(pcrit_ctx *c, void *hip_stream, const float *field,
   int kmax = 0, group_end[kMaxLevels];
   unsigned gen = 0;
   const bool timed = level_ms_host != nullptr;
+  const bool count = reclassified_host != nullptr;
   int st = enqueue_progressive(c, s, field, nx, ny, nz, codes, crit, crit_codes,
-                               crit_capacity, timed, cb, user, &kmax, group_end, &gen);
+                               crit_capacity, timed, count, cb, user, &kmax, group_end,
+                               &gen);
   if (st) return st;
   if (read_status(c, s)) return PCRIT_E_HIP;
   if (level_offsets_host)
@@ -646,7 +681,7 @@ int pcrit_progressive_async(pcrit_ctx *c, void *hip_stream, const float *field,
   unsigned gen = 0;
   bool published = false;
   int st = enqueue_progressive(c, s, field, nx, ny, nz, codes, crit, nullptr,
-                               crit_capacity, false, nullptr, nullptr, &kmax,
+                               crit_capacity, false, false, nullptr, nullptr, &kmax,
                                group_end, &gen, level_offsets_dev, &published);
   if (st) return st;
   if (published) return PCRIT_OK;

@@ -70,4 +70,47 @@ void build(const int (*off)[D], uint8_t *table) {
 void build_link_table3(uint8_t *table) { build<3, 14>(kOff3, table); }
 void build_link_table2(uint8_t *table) { build<2, 6>(kOff2, table); }
 
+void build_quad_table3(const uint8_t *table3, uint8_t *quad) {
+  // where each neighbour offset of the link-pattern table sits in the quad
+  // index: positive direction j (its bit is 1 iff the neighbour is lower)
+  // or negative direction j (bit 8 + j, 1 iff the neighbour is upper)
+  int dir[14], neg[14];
+  for (int k = 0; k < 14; k++) {
+    dir[k] = -1;
+    for (int j = 0; j < 7; j++) {
+      if (kQD[j][0] == kOff3[k][0] && kQD[j][1] == kOff3[k][1] && kQD[j][2] == kOff3[k][2]) {
+        dir[k] = j;
+        neg[k] = 0;
+      }
+      if (kQD[j][0] == -kOff3[k][0] && kQD[j][1] == -kOff3[k][1] && kQD[j][2] == -kOff3[k][2]) {
+        dir[k] = j;
+        neg[k] = 1;
+      }
+    }
+  }
+  for (unsigned i = 0; i < (unsigned)kQuadTableSize; i++) {
+    const unsigned p = i & 0x7Fu, n = (i >> 8) & 0x7Fu;
+    unsigned m = 0;  // bit k = 1 iff neighbour k comes after the vertex
+    for (int k = 0; k < 14; k++) {
+      const unsigned upper = neg[k] ? (n >> dir[k]) & 1u : ((p >> dir[k]) & 1u) ^ 1u;
+      m |= upper << k;
+    }
+    quad[i] = (i & 0x8000u) ? 0 : table3[m];
+  }
+  // x-boundary codes: the absent neighbours forced upper, then lower (the
+  // rule the kernels apply to other boundary vertices), by index without
+  // the absent bits
+  auto boundary = [&](unsigned idx, unsigned A) {
+    const unsigned base = idx & ~A;
+    const unsigned eL = quad[base | (A & kQNeg)], eU = quad[base | (A & kQPos)];
+    const unsigned holes = ((eL >> 3) > 1u) | ((eU & 7u) > 1u);
+    return (uint8_t)((eL & 7u) | (eU & 0x38u) | 0x40u | (holes << 7));
+  };
+  uint8_t *txl = quad + kQuadTableSize, *txh = quad + kQuadTableSize + 1024;
+  for (unsigned c = 0; c < 1024; c++) {
+    txl[c] = boundary((c & 0x7Fu) | ((c >> 7) << 12), quad_side(0, -1));
+    txh[c] = boundary(((c & 7u) << 4) | ((c >> 3) << 8), quad_side(0, 1));
+  }
+}
+
 }  // namespace pcrit

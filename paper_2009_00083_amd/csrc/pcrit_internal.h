@@ -39,6 +39,33 @@ constexpr unsigned side_mask2(int axis, int side) {
 void build_link_table3(uint8_t *table);
 void build_link_table2(uint8_t *table);
 
+// Quad tiles (full-resolution and stride-2 levels of 3D grids, four
+// columns per lane).  Their table index is built from edge signs: the seven
+// neighbour offsets with all components >= 0 ("positive" directions, the
+// later neighbours in index order) in this order,
+constexpr int kQD[7][3] = {{1, 0, 0}, {1, 1, 0}, {1, 0, 1}, {1, 1, 1},
+                           {0, 1, 0}, {0, 0, 1}, {0, 1, 1}};
+// bit j (0..6): sign bit of f(v + d_j) - f(v), i.e. 1 iff that neighbour
+// comes before v; bit 8 + j: sign bit of f(v) - f(v - d_j), i.e. 1 iff
+// v - d_j comes after v; bit 7 carries no information and bit 15 is 0.
+constexpr int kQuadTableSize = 1 << 15;
+// Followed by the codes of x-boundary vertices (two tables of 1024 bytes):
+// column 0 indexed by bits 0-6 and 12-14 of the index (the others are the
+// absent neighbours), column mx-1 by bits 4-6 and 8-14.
+constexpr int kQuadTableBytes = kQuadTableSize + 2048;
+constexpr unsigned kQPos = 0x007Fu, kQNeg = 0x7F00u;
+// Absent-neighbour bits of a vertex on the low (side -1) or high (+1) end
+// of axis a (0 = x, 1 = y, 2 = z) in that index.
+constexpr unsigned quad_side(int axis, int side) {
+  unsigned m = 0;
+  for (int j = 0; j < 7; j++)
+    if (kQD[j][axis] == 1) m |= side < 0 ? 1u << (8 + j) : 1u << j;
+  return m;
+}
+// The quad table from the link-pattern table: entry of index i = entry of
+// the polarity mask i describes.
+void build_quad_table3(const uint8_t *table3, uint8_t *quad);  // kQuadTableBytes
+
 // Compaction chunk: 256 threads x 4 words of 64 bits (65536 vertices).
 constexpr int kCompactThreads = 256;
 constexpr int kCompactWordsPerThread = 4;
@@ -173,6 +200,45 @@ hipError_t launch_publish_offsets(const int64_t *level_base, int n,
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
                            bool write_masks, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st);
+
+// Quad tiles: 256 level columns (four per lane, one 16-byte load per row for
+// a full-resolution level, two for a stride-2 level) by kQuadRows rows by
+// zchunk planes per wave.
+constexpr int kQuadCols = 256;
+#ifndef PCRIT_QUAD_ROWS
+#define PCRIT_QUAD_ROWS 2
+#endif
+#ifndef PCRIT_QUAD_SLOTS
+#define PCRIT_QUAD_SLOTS 3
+#endif
+#ifndef PCRIT_QUAD_ZCHUNK
+#define PCRIT_QUAD_ZCHUNK 16
+#endif
+constexpr int kQuadRows = PCRIT_QUAD_ROWS;
+constexpr int kQuadSlots = PCRIT_QUAD_SLOTS;  // planes held in registers per wave
+constexpr int kQuadZChunk = PCRIT_QUAD_ZCHUNK;
+#ifndef PCRIT_QUAD_WAVES
+#define PCRIT_QUAD_WAVES 4
+#endif
+constexpr int kQuadWavesPerSimd = PCRIT_QUAD_WAVES;  // occupancy the kernel is built for
+#ifndef PCRIT_QUAD_BLOCK_WAVES
+#define PCRIT_QUAD_BLOCK_WAVES 4
+#endif
+constexpr int kQuadBlockWaves = PCRIT_QUAD_BLOCK_WAVES;  // waves sharing one copy of the tables
+struct QuadArgs {
+  const float *f;        // full-resolution field
+  int64_t fbytes;        // its size in bytes (loads past it read zeros)
+  uint8_t *codes;        // full-resolution code bytes, or null
+  const uint8_t *lut;    // quad table (device, kQuadTableSize bytes)
+  LevelDesc lv;
+  unsigned *nan_flag;
+  unsigned gen;
+};
+// Level geometry of a quad launch; whether a level can take one (stride 1
+// or 2, 16-byte aligned rows).
+void plan_level_quad(LevelDesc &l);
+bool quad_eligible(const float *field, int64_t nx, int64_t s, int dim);
+hipError_t launch_classify_quad(const QuadArgs &a, hipStream_t st);
 
 // Fixed scratch of the allocation-free entry point (one copy per GPU):
 // critical bitmask words, then per-chunk counts at a 256-byte boundary.

@@ -260,9 +260,16 @@ def test_progressive_gsin256(ctx, dev):
     f = fieldgen.config_field("gsin256")
     log("gsin256 progressive, per-level oracle")
     p = check_progressive(ctx, dev, f)
-    assert p.reclassified[0] == 0
-    assert (p.reclassified[1:] > 0).all()
-    log("reclassified per level", p.reclassified.tolist())
+    ft = torch.from_numpy(f).to(dev)
+    q = pc.progressive(ft, ctx=ctx, with_crit_codes=True, count_reclassified=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(q.offsets, p.offsets)
+    n = int(p.offsets[-1])
+    assert torch.equal(q.crit[:n], p.crit[:n]) and torch.equal(q.codes, p.codes)
+    assert torch.equal(q.crit_codes[:n], p.crit_codes[:n])
+    assert q.reclassified[0] == 0
+    assert (q.reclassified[1:] > 0).all()
+    log("reclassified per level", q.reclassified.tolist())
 
 
 def test_progressive_gauss64(ctx, dev):
@@ -319,10 +326,10 @@ def test_progressive_unfused_and_reclassified(ctx, dev, shape, gen):
          fieldgen.gaussian_field(shape, 8, 6, noise=("uniform", 1e-3)))
     ft = torch.from_numpy(f).to(dev)
     seen = []
-    p1 = pc.progressive(ft, ctx=ctx, with_crit_codes=True,
+    p1 = pc.progressive(ft, ctx=ctx, with_crit_codes=True, count_reclassified=True,
                         callback=lambda k, n, u: seen.append((k, n)))
     torch.cuda.synchronize()
-    p2 = pc.progressive(ft, ctx=ctx, with_crit_codes=True)
+    p2 = pc.progressive(ft, ctx=ctx, with_crit_codes=True, count_reclassified=True)
     torch.cuda.synchronize()
     assert [k for k, _ in seen] == list(p1.levels)
     assert [n for _, n in seen] == list(np.diff(p1.offsets))
@@ -560,7 +567,6 @@ def test_full_size(ctx, dev, name):
         if 0 < k <= 2:
             d = gpu_classify(ctx, dev, f, k)
             assert_same(f, k, d, lref, f"{name} level {k}")
-    log("reclassified per level", p.reclassified.tolist())
     # the asynchronous entry point (the bench's) enqueues the same work
     codes_a, crit_a, offs_a = pc.progressive_async(ft, ctx=ctx)
     torch.cuda.synchronize()
