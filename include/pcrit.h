@@ -253,6 +253,119 @@ int pcrit_preview_f1(int64_t nx, int64_t ny, int64_t nz, int level,
                      const uint8_t *exact_codes_host, int64_t n_exact,
                      double *f1_host, int64_t *matches_host);
 
+/* Host-only metric: as pcrit_preview_f1, but each preview point i carries
+ * its own level preview_levels_host[i] (match distance 2^level), for
+ * previews that mix levels (regions refined to different depths). */
+int pcrit_preview_f1_levels(int64_t nx, int64_t ny, int64_t nz,
+                            const uint32_t *preview_host,
+                            const uint8_t *preview_codes_host,
+                            const uint8_t *preview_levels_host, int64_t n_preview,
+                            const uint32_t *exact_host,
+                            const uint8_t *exact_codes_host, int64_t n_exact,
+                            double *f1_host, int64_t *matches_host);
+
+/* ------------------------------------------------------------------------
+ * Region timeline and learned refinement order (3D grids).
+ *
+ * The paper classifies every vertex; it has no hierarchy and no refinement
+ * order.  Here the progressive call can refine its full-resolution and
+ * stride-2 levels region by region: a region is a block of region_edge
+ * full-resolution rows by region_edge planes (all columns), numbered
+ * rz * nry + ry with nry = ceil(ny / region_edge), and a preview at time t
+ * shows each region at the finest level whose pass over that region has
+ * finished.  The order only changes when a region's previews appear; every
+ * vertex of every level is classified either way, so the lists and codes
+ * are those of pcrit_progressive.
+ *
+ * A small network can choose the order: inputs are the 27 samples around a
+ * vertex of a coarse level (the 3x3x3 neighbourhood at that level's stride,
+ * z slowest, x fastest, minus the centre sample, divided by the largest
+ * magnitude among them, 0 if all are equal), then log2((n_min - 1) / 2^level)
+ * / 8 with n_min the shortest axis, then 4 zeros: 32 BF16 values per vertex
+ * (uint16 bit patterns).  The network is 32 -> 64 -> 64 -> 1: h1 = GELU(x W1
+ * + b1), h2 = GELU(h1 W2 + b2), logit = h2 . w3 + b3, GELU(u) = u/2 (1 +
+ * erf(u / sqrt 2)).  Parameters: PCRIT_MLP_PARAMS floats, FP32, in the
+ * order W1 [32][64] (input-major), b1 [64], W2 [64][64], b2 [64], w3 [64],
+ * b3.  The kernels round W1, W2 and w3 to BF16 (nearest even), x and h1 are
+ * BF16, products accumulate in FP32; b1, b2, b3, h2 and the output are FP32.
+ * Its training target for a vertex v of level k (stride s) is 1 iff a
+ * full-resolution vertex within [v - s/2, v + s/2) on every axis is critical
+ * (level-0 code).  A region's score is the sum of the sigmoid of its
+ * vertices' logits; regions are refined by decreasing score.
+ * ---------------------------------------------------------------------- */
+#define PCRIT_MLP_PARAMS 6337
+#define PCRIT_MLP_INPUTS 32
+
+/* Host-only.  Coarse level whose vertices the learned order scores (about
+ * 64 cells along the shortest axis, at least 1).  3D only. */
+int pcrit_mlp_feature_level(int64_t nx, int64_t ny, int64_t nz, int *level_host);
+
+/* Network inputs of every vertex of level `level` (>= 1, 3D): X is device
+ * memory, 16-byte aligned, n_level x 32 uint16 (BF16), level-local C order. */
+int pcrit_mlp_features(pcrit_ctx *ctx, void *hip_stream, const float *field,
+                       int64_t nx, int64_t ny, int64_t nz, int level, uint16_t *X);
+
+/* Training targets of the vertices of level `level` from full-resolution
+ * level-0 codes (device): labels[i] = 0 or 1 (device, n_level bytes). */
+int pcrit_mlp_labels(pcrit_ctx *ctx, void *hip_stream, const uint8_t *codes,
+                     int64_t nx, int64_t ny, int64_t nz, int level, uint8_t *labels);
+
+/* logits[i] of the n inputs X (all device memory). */
+int pcrit_mlp_forward(pcrit_ctx *ctx, void *hip_stream, const float *params,
+                      const uint16_t *X, int64_t n, float *logits);
+
+/* Gradient of the mean binary cross-entropy of the logits of X against
+ * labels (0/1) with respect to params: written to grad (PCRIT_MLP_PARAMS
+ * floats, overwritten); *loss (device float) receives the sum of the
+ * per-sample losses.  The weight-gradient products run on the matrix cores
+ * with BF16 operands (the back-propagated signals and the activations
+ * rounded to BF16, FP32 accumulation), so the gradient is the exact one of
+ * the forward pass above to about 1 %.  All pointers are device memory;
+ * n >= 1. */
+int pcrit_mlp_backward(pcrit_ctx *ctx, void *hip_stream, const float *params,
+                       const uint16_t *X, const uint8_t *labels, int64_t n,
+                       float *grad, float *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * number step >= 1) on params with moments m and v (device, each
+ * PCRIT_MLP_PARAMS floats, m and v zero before the first step). */
+int pcrit_mlp_adam(pcrit_ctx *ctx, void *hip_stream, float *params,
+                   const float *grad, float *m, float *v, float lr, int step);
+
+/* Host-only.  Number of regions of edge region_edge (a power of two,
+ * >= 32) of a 3D grid: ceil(ny / edge) * ceil(nz / edge); at most 1024. */
+int pcrit_region_count(int64_t nx, int64_t ny, int64_t nz, int region_edge,
+                       int *n_host);
+
+/* The progressive classification of pcrit_progressive (no list codes, no
+ * re-classification count) with a timeline: the leading small levels run in
+ * two launches (levels of at most 2^18 vertices, then the others up to
+ * 2^22), and each later level that takes the quad tiles is classified region
+ * by region in the chosen order, the wave that finishes a region's last
+ * tile recording the GPU clock.  The call synchronises at its end.
+ *   order_mode        0: regions in id order; 1: rank_host[r] is the
+ *                     position of region r (a permutation); 2: learned, from
+ *                     the network with parameters mlp_params (device), run
+ *                     on the GPU before the first region-refined level (the
+ *                     scores of level pcrit_mlp_feature_level, ties by id);
+ *                     then rank_host, if not NULL, receives the positions
+ *                     used (the identity if no level is refined by regions)
+ *   level_offsets_host  as for pcrit_progressive (k_max+2 entries)
+ *   level_ms_host     k_max+1 doubles: milliseconds from the call's first
+ *                     kernel until level k's list is complete (index
+ *                     i = k_max - k)
+ *   region_ms_host    (k_max+1) x n_regions doubles: [i][r] = milliseconds
+ *                     until level k of region r was classified (for levels
+ *                     not refined by regions, the level's list time)
+ * Errors as pcrit_progressive; PCRIT_E_ARG for 2D grids, a bad order or
+ * edge. */
+int pcrit_progressive_timeline(pcrit_ctx *ctx, void *hip_stream, const float *field,
+                               int64_t nx, int64_t ny, int64_t nz, uint8_t *codes,
+                               uint32_t *crit, int64_t crit_capacity, int region_edge,
+                               int order_mode, int32_t *rank_host,
+                               const float *mlp_params, int64_t *level_offsets_host,
+                               double *level_ms_host, double *region_ms_host);
+
 #ifdef __cplusplus
 }
 #endif

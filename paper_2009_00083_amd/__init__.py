@@ -9,7 +9,10 @@ raises.
 """
 from .binding import (  # noqa: F401
     PcritError, Context, classify, classify_noalloc, progressive, progressive_async, max_level, level_dims,
-    link_table, preview_f1, library_path, decode, is_critical, point_type,
+    link_table, preview_f1, preview_f1_levels, library_path, decode, is_critical, point_type,
+    region_count, mlp_feature_level, mlp_features, mlp_labels, mlp_forward, mlp_backward,
+    mlp_adam, progressive_timeline, MLP_PARAMS, MLP_INPUTS,
     E_ARG, E_DIMS, E_LEVEL, E_CAPACITY, E_NAN, E_HIP, E_OOM, E_SCRATCH,
     NOALLOC_SCRATCH_BYTES,
 )
+from . import learned_order  # noqa: F401,E402

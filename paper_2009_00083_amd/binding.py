@@ -28,7 +28,12 @@ EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_max_level", "pcrit_level_dims", "pcrit_link_table",
             "pcrit_classify", "pcrit_classify_noalloc", "pcrit_progressive",
             "pcrit_progressive_async",
-            "pcrit_set_kernel_timing", "pcrit_kernel_ms", "pcrit_preview_f1")
+            "pcrit_set_kernel_timing", "pcrit_kernel_ms", "pcrit_preview_f1",
+            "pcrit_preview_f1_levels", "pcrit_mlp_feature_level", "pcrit_mlp_features",
+            "pcrit_mlp_labels", "pcrit_mlp_forward", "pcrit_mlp_backward",
+            "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline")
+MLP_PARAMS = 6337
+MLP_INPUTS = 32
 
 
 class PcritError(RuntimeError):
@@ -83,6 +88,26 @@ def _load():
     lib.pcrit_preview_f1.argtypes = [i64, i64, i64, i32, vp, vp, i64, vp, vp,
                                      i64, ctypes.POINTER(ctypes.c_double), p64]
     lib.pcrit_preview_f1.restype = i32
+    lib.pcrit_preview_f1_levels.argtypes = [i64, i64, i64, vp, vp, vp, i64, vp, vp, i64,
+                                            ctypes.POINTER(ctypes.c_double), p64]
+    lib.pcrit_preview_f1_levels.restype = i32
+    lib.pcrit_mlp_feature_level.argtypes = [i64, i64, i64, ctypes.POINTER(i32)]
+    lib.pcrit_mlp_feature_level.restype = i32
+    lib.pcrit_mlp_features.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
+    lib.pcrit_mlp_features.restype = i32
+    lib.pcrit_mlp_labels.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp]
+    lib.pcrit_mlp_labels.restype = i32
+    lib.pcrit_mlp_forward.argtypes = [vp, vp, vp, vp, i64, vp]
+    lib.pcrit_mlp_forward.restype = i32
+    lib.pcrit_mlp_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+    lib.pcrit_mlp_backward.restype = i32
+    lib.pcrit_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_float, i32]
+    lib.pcrit_mlp_adam.restype = i32
+    lib.pcrit_region_count.argtypes = [i64, i64, i64, i32, ctypes.POINTER(i32)]
+    lib.pcrit_region_count.restype = i32
+    lib.pcrit_progressive_timeline.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, i32,
+                                               i32, vp, vp, vp, vp, vp]
+    lib.pcrit_progressive_timeline.restype = i32
     _lib = lib
     return lib
 
@@ -480,3 +505,196 @@ def point_type(codes):
     t[nu == 0] = 2
     t[nl == 0] = 1
     return t
+
+
+# ---------------------------------------------------------------------------
+# Learned refinement order and region timeline
+# ---------------------------------------------------------------------------
+def region_count(shape, edge: int) -> int:
+    nx, ny, nz = _shape3(shape)
+    n = ctypes.c_int(0)
+    _check(_load().pcrit_region_count(nx, ny, nz, int(edge), ctypes.byref(n)),
+           "region_count")
+    return n.value
+
+
+def mlp_feature_level(shape) -> int:
+    nx, ny, nz = _shape3(shape)
+    k = ctypes.c_int(0)
+    _check(_load().pcrit_mlp_feature_level(nx, ny, nz, ctypes.byref(k)),
+           "mlp_feature_level")
+    return k.value
+
+
+def mlp_features(field, level: int, *, ctx: Optional[Context] = None, out=None,
+                 stream=None):
+    """Network inputs (n_level x 32, bfloat16) of every vertex of level
+    ``level``."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    c = _ctx_for(field, ctx)
+    m = level_dims(field.shape, level)
+    n = m[0] * m[1] * m[2]
+    if out is None:
+        out = torch.empty((n, MLP_INPUTS), dtype=torch.bfloat16, device=field.device)
+    check_buffer("out", out, torch.bfloat16, field.device, numel=n * MLP_INPUTS)
+    _check(_load().pcrit_mlp_features(c.handle, _stream_handle(field, stream), _ptr(field),
+                                      nx, ny, nz, int(level), _ptr(out)), "mlp_features")
+    return out
+
+
+def mlp_labels(codes, level: int, *, ctx: Optional[Context] = None, out=None,
+               stream=None):
+    """Training targets (uint8 0/1) of the vertices of level ``level`` from
+    full-resolution level-0 codes."""
+    import torch
+    if codes.dtype != torch.uint8 or not codes.is_contiguous():
+        raise PcritError(E_ARG, "codes must be contiguous uint8")
+    nx, ny, nz = _shape3(codes.shape)
+    c = _ctx_for(codes, ctx)
+    m = level_dims(codes.shape, level)
+    n = m[0] * m[1] * m[2]
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=codes.device)
+    check_buffer("out", out, torch.uint8, codes.device, numel=n)
+    _check(_load().pcrit_mlp_labels(c.handle, _stream_handle(codes, stream), _ptr(codes),
+                                    nx, ny, nz, int(level), _ptr(out)), "mlp_labels")
+    return out
+
+
+def _check_params(params, device):
+    import torch
+    return check_buffer("params", params, torch.float32, device, numel=MLP_PARAMS)
+
+
+def mlp_forward(params, X, *, ctx: Optional[Context] = None, out=None, stream=None):
+    """Logits (float32) of the inputs X (n x 32 bfloat16)."""
+    import torch
+    check_buffer("X", X, torch.bfloat16, X.device)
+    n = X.numel() // MLP_INPUTS
+    _check_params(params, X.device)
+    c = _ctx_for(X, ctx)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=X.device)
+    check_buffer("out", out, torch.float32, X.device, min_numel=n)
+    _check(_load().pcrit_mlp_forward(c.handle, _stream_handle(X, stream), _ptr(params),
+                                     _ptr(X), n, _ptr(out)), "mlp_forward")
+    return out
+
+
+def mlp_backward(params, X, labels, *, ctx: Optional[Context] = None, grad=None,
+                 loss=None, stream=None):
+    """(grad, loss_sum): gradient of the mean binary cross-entropy."""
+    import torch
+    check_buffer("X", X, torch.bfloat16, X.device)
+    n = X.numel() // MLP_INPUTS
+    _check_params(params, X.device)
+    check_buffer("labels", labels, torch.uint8, X.device, numel=n)
+    c = _ctx_for(X, ctx)
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    check_buffer("grad", grad, torch.float32, X.device, numel=MLP_PARAMS)
+    check_buffer("loss", loss, torch.float32, X.device, min_numel=1)
+    _check(_load().pcrit_mlp_backward(c.handle, _stream_handle(X, stream), _ptr(params),
+                                      _ptr(X), _ptr(labels), n, _ptr(grad), _ptr(loss)),
+           "mlp_backward")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, lr: float, step: int, *, ctx: Optional[Context] = None,
+             stream=None):
+    import torch
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        check_buffer(name, t, torch.float32, params.device, numel=MLP_PARAMS)
+    c = _ctx_for(params, ctx)
+    _check(_load().pcrit_mlp_adam(c.handle, _stream_handle(params, stream), _ptr(params),
+                                  _ptr(grad), _ptr(m), _ptr(v), ctypes.c_float(lr),
+                                  int(step)), "mlp_adam")
+
+
+@dataclass
+class TimelineResult:
+    codes: "object"
+    crit: "object"
+    levels: List[int]
+    offsets: np.ndarray
+    level_ms: np.ndarray         # per level index i = k_max - k
+    region_ms: np.ndarray        # (levels, regions)
+    region_edge: int
+    status: int
+    rank: np.ndarray             # position of each region in the order used
+
+    def level_list(self, level: int):
+        i = self.levels.index(level)
+        return self.crit[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+
+def progressive_timeline(field, region_edge: int = 64, *, order=None, params=None,
+                         ctx: Optional[Context] = None, capacity: Optional[int] = None,
+                         codes=None, crit=None, stream=None,
+                         check: bool = True) -> TimelineResult:
+    """Progressive classification with region-by-region refinement of the
+    large levels and per-region completion times.  ``order``: None (region
+    id order), or an int array of region ranks (rank[r] = position of
+    region r); ``params``: the network's parameters (device float32) for the
+    learned order (then ``order`` must be None)."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    lib = _load()
+    c = _ctx_for(field, ctx)
+    kmax, total = _hierarchy(tuple(field.shape))
+    nreg = region_count(field.shape, region_edge)
+    capacity = _capacity(capacity, crit, total)
+    if codes is None:
+        codes = torch.zeros(field.shape, dtype=torch.uint8, device=field.device)
+    check_buffer("codes", codes, torch.uint8, field.device, numel=field.numel())
+    if crit is None:
+        crit = torch.empty(max(capacity, 1), dtype=torch.int32, device=field.device)
+    check_buffer("crit", crit, torch.int32, field.device, min_numel=capacity)
+    mode, rank = 0, None
+    if params is not None:
+        if order is not None:
+            raise PcritError(E_ARG, "give either an order or network parameters")
+        _check_params(params, field.device)
+        mode = 2
+        rank = np.zeros(nreg, np.int32)
+    elif order is not None:
+        rank = np.ascontiguousarray(order, dtype=np.int32)
+        if rank.shape != (nreg,):
+            raise PcritError(E_ARG, f"order must have {nreg} entries")
+        mode = 1
+    offs = np.zeros(kmax + 2, np.int64)
+    lms = np.zeros(kmax + 1, np.float64)
+    rms = np.zeros((kmax + 1, nreg), np.float64)
+    st = lib.pcrit_progressive_timeline(
+        c.handle, _stream_handle(field, stream), _ptr(field), nx, ny, nz, _ptr(codes),
+        _ptr(crit), int(capacity), int(region_edge), mode,
+        None if rank is None else rank.ctypes.data, _ptr(params), offs.ctypes.data,
+        lms.ctypes.data, rms.ctypes.data)
+    if check and st not in (0, E_CAPACITY):
+        raise PcritError(st, "pcrit_progressive_timeline")
+    return TimelineResult(codes, crit, list(range(kmax, -1, -1)), offs, lms, rms,
+                          int(region_edge), st,
+                          rank if rank is not None else np.arange(nreg, dtype=np.int32))
+
+
+def preview_f1_levels(shape, preview, preview_codes, preview_levels, exact, exact_codes):
+    """Host metric with a level per preview point: (F1, matches)."""
+    nx, ny, nz = _shape3(shape)
+    p = np.ascontiguousarray(preview, dtype=np.uint32)
+    pc = np.ascontiguousarray(preview_codes, dtype=np.uint8)
+    pl = np.ascontiguousarray(preview_levels, dtype=np.uint8)
+    e = np.ascontiguousarray(exact, dtype=np.uint32)
+    ec = np.ascontiguousarray(exact_codes, dtype=np.uint8)
+    if not (len(p) == len(pc) == len(pl)) or len(e) != len(ec):
+        raise PcritError(E_ARG, "list lengths differ")
+    f1 = ctypes.c_double(0)
+    mt = ctypes.c_int64(0)
+    _check(_load().pcrit_preview_f1_levels(nx, ny, nz, p.ctypes.data, pc.ctypes.data,
+                                           pl.ctypes.data, len(p), e.ctypes.data,
+                                           ec.ctypes.data, len(e), ctypes.byref(f1),
+                                           ctypes.byref(mt)), "preview_f1_levels")
+    return f1.value, mt.value
+

@@ -2,6 +2,7 @@
 // direct and the progressive drivers.  Every step of the classification runs
 // in the kernels of classify.hip; this file only validates, sizes and
 // enqueues.
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -15,6 +16,8 @@ using namespace pcrit;
 
 static_assert(kNoAllocScratchBytes == PCRIT_NOALLOC_SCRATCH_BYTES,
               "scratch size of the header and of the library");
+static_assert(kMlpParams == PCRIT_MLP_PARAMS && kMlpIn == PCRIT_MLP_INPUTS,
+              "network size of the header and of the library");
 
 namespace {
 
@@ -108,6 +111,8 @@ struct pcrit_ctx {
   hipEvent_t kev[2][kMaxLevels][2] = {};
   bool kused[2][kMaxLevels] = {};
   hipEvent_t last_kev = nullptr;
+  void *tl = nullptr;  // region timeline and learned-order scratch
+  int64_t tl_bytes = 0;
 };
 
 namespace {
@@ -187,11 +192,22 @@ void launch_needs(const Step *steps, int n, bool with_codes, int64_t *words,
 // the others keep dense level codes for crit_codes.
 // `bits` and `counts` are the launch's scratch (the context's, or the fixed
 // array of the allocation-free entry point).
+// Region timeline of a quad level: tiles taken region by region in rank
+// order, each region's completion stamped (see QuadArgs).
+struct RegionHooks {
+  int E = 0, nry = 0, nregions = 0;
+  const int *rank = nullptr;  // device, per region
+  int *tile_list = nullptr, *scratch = nullptr;
+  unsigned *left = nullptr;
+  uint64_t *stamp = nullptr;  // this level's row of region stamps
+};
+
 int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   const Step *steps, int n, uint8_t *codes, uint32_t *crit,
                   uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
                   unsigned gen, bool final_group, uint64_t *bits, int *counts,
-                  int64_t *publish = nullptr, int publish_n = 0) {
+                  int64_t *publish = nullptr, int publish_n = 0,
+                  const RegionHooks *rh = nullptr) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -273,9 +289,24 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     q.codes = a.lv[0].write_codes ? codes : nullptr;
     q.lut = c->lutq;
     q.lv = a.lv[0];
-    plan_level_quad(q.lv);
     q.nan_flag = a.nan_flag;
     q.gen = gen;
+    if (rh) {
+      const int s = (int)s0.g.s;
+      plan_level_quad(q.lv, std::min(kQuadZChunk, rh->E / s));
+      if (launch_region_tiles(q.lv, kQuadRows, s, rh->E, rh->nry, rh->nregions, rh->rank,
+                              rh->tile_list, rh->left, rh->scratch, st) != hipSuccess)
+        return PCRIT_E_HIP;
+      q.tile_list = rh->tile_list;
+      q.xcd_off = region_xcd_off(rh->scratch, rh->nregions);
+      q.queue = region_queue(rh->scratch, rh->nregions);
+      q.region_left = rh->left;
+      q.region_stamp = rh->stamp;
+      q.region_edge = rh->E;
+      q.nry = rh->nry;
+    } else {
+      plan_level_quad(q.lv);
+    }
     if (launch_classify_quad(q, st) != hipSuccess) return PCRIT_E_HIP;
   } else if (launch_classify(a, dim, !fused && s0.mask_read >= 0,
                              !fused && s0.mask_write >= 0, st) != hipSuccess) {
@@ -424,6 +455,7 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->masks[0]);
   hipFree(c->masks[1]);
   hipFree(c->reclass_acc);
+  hipFree(c->tl);
   hipFree(c->status);
   if (c->h_status) hipHostFree(c->h_status);
   if (c->ev_start) hipEventDestroy(c->ev_start);
@@ -715,6 +747,298 @@ int pcrit_kernel_ms(pcrit_ctx *c, float *classify_ms_host,
     }
   }
   return PCRIT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned refinement order and the region timeline
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Level of the learned order's features: about 64 cells along the shortest
+// axis (at least level 1).
+int feature_level(int64_t nx, int64_t ny, int64_t nz, int kmax) {
+  const int64_t nmin = std::min(std::min(nx, ny), nz) - 1;
+  int best = 1;
+  double err = 1e30;
+  for (int k = 1; k <= kmax; k++) {
+    const double e = fabs(log2((double)nmin / (double)((int64_t)1 << k)) - 6.0);
+    if (e < err) {
+      err = e;
+      best = k;
+    }
+  }
+  return std::min(best, kmax);
+}
+
+float resolution_feature(int64_t nx, int64_t ny, int64_t nz, int level) {
+  const int64_t nmin = std::min(std::min(nx, ny), nz) - 1;
+  return (float)(log2((double)nmin / (double)((int64_t)1 << level)) / 8.0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcrit_mlp_feature_level(int64_t nx, int64_t ny, int64_t nz, int *level_host) {
+  if (!level_host || nz < 2) return PCRIT_E_ARG;
+  const int st = check_dims(nx, ny, nz);
+  if (st) return st;
+  const int kmax = max_level_of(nx, ny, nz);
+  if (kmax < 1) return PCRIT_E_DIMS;
+  *level_host = feature_level(nx, ny, nz, kmax);
+  return PCRIT_OK;
+}
+
+int pcrit_mlp_features(pcrit_ctx *c, void *hip_stream, const float *field, int64_t nx,
+                       int64_t ny, int64_t nz, int level, uint16_t *X) {
+  if (!c || !field || !X || nz < 2 || level < 1) return PCRIT_E_ARG;
+  Geom g;
+  const int st = make_geom(nx, ny, nz, level, &g);
+  if (st) return st;
+  if (misaligned(X, 16)) return PCRIT_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  return launch_mlp_features(field, nx, ny, nz, (int)g.s, (int)g.mx, (int)g.my, (int)g.mz,
+                             resolution_feature(nx, ny, nz, level), X,
+                             (hipStream_t)hip_stream) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
+
+int pcrit_mlp_labels(pcrit_ctx *c, void *hip_stream, const uint8_t *codes, int64_t nx,
+                     int64_t ny, int64_t nz, int level, uint8_t *labels) {
+  if (!c || !codes || !labels || nz < 2 || level < 1) return PCRIT_E_ARG;
+  Geom g;
+  const int st = make_geom(nx, ny, nz, level, &g);
+  if (st) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  return launch_mlp_labels(codes, nx, ny, nz, (int)g.s, (int)g.mx, (int)g.my, (int)g.mz, labels,
+                           (hipStream_t)hip_stream) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
+
+int pcrit_mlp_forward(pcrit_ctx *c, void *hip_stream, const float *params, const uint16_t *X,
+                      int64_t n, float *logits) {
+  if (!c || !params || n < 0 || (n > 0 && (!X || !logits)) || misaligned(X, 16))
+    return PCRIT_E_ARG;
+  if (n == 0) return PCRIT_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  return launch_mlp_forward(params, X, n, logits, (hipStream_t)hip_stream) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
+
+int pcrit_mlp_backward(pcrit_ctx *c, void *hip_stream, const float *params, const uint16_t *X,
+                       const uint8_t *labels, int64_t n, float *grad, float *loss) {
+  if (!c || !params || !grad || !loss || n < 1 || !X || !labels || misaligned(X, 16))
+    return PCRIT_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  return launch_mlp_backward(params, X, labels, n, grad, loss, (hipStream_t)hip_stream) ==
+                 hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
+
+int pcrit_mlp_adam(pcrit_ctx *c, void *hip_stream, float *params, const float *grad, float *m,
+                   float *v, float lr, int step) {
+  if (!c || !params || !grad || !m || !v || step < 1 || !(lr > 0.f)) return PCRIT_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  return launch_mlp_adam(params, grad, m, v, lr, step, (hipStream_t)hip_stream) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
+
+int pcrit_region_count(int64_t nx, int64_t ny, int64_t nz, int region_edge, int *n_host) {
+  if (!n_host || nz < 2 || region_edge < 32 || region_edge > (1 << 20) ||
+      (region_edge & (region_edge - 1)))
+    return PCRIT_E_ARG;
+  const int st = check_dims(nx, ny, nz);
+  if (st) return st;
+  const int64_t n = ((ny + region_edge - 1) / region_edge) * ((nz + region_edge - 1) / region_edge);
+  if (n > kMaxRegions) return PCRIT_E_ARG;
+  *n_host = (int)n;
+  return PCRIT_OK;
+}
+
+int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *field, int64_t nx,
+                               int64_t ny, int64_t nz, uint8_t *codes, uint32_t *crit,
+                               int64_t crit_capacity, int region_edge, int order_mode,
+                               int32_t *rank_host, const float *mlp_params,
+                               int64_t *level_offsets_host, double *level_ms_host,
+                               double *region_ms_host) {
+  if (!c || !field || !codes || crit_capacity < 0 || (crit_capacity > 0 && !crit) ||
+      !level_offsets_host || !level_ms_host || !region_ms_host)
+    return PCRIT_E_ARG;
+  if (misaligned(field, 4) || (crit && misaligned(crit, 4))) return PCRIT_E_ARG;
+  int nregions = 0;
+  int st = pcrit_region_count(nx, ny, nz, region_edge, &nregions);
+  if (st) return st;
+  if (order_mode < 0 || order_mode > 2 || (order_mode == 1 && !rank_host) ||
+      (order_mode == 2 && !mlp_params))
+    return PCRIT_E_ARG;
+  if (order_mode == 1) {  // a permutation of the regions
+    std::vector<char> seen(nregions, 0);
+    for (int r = 0; r < nregions; r++) {
+      const int k = rank_host[r];
+      if (k < 0 || k >= nregions || seen[k]) return PCRIT_E_ARG;
+      seen[k] = 1;
+    }
+  }
+  const int kmax = max_level_of(nx, ny, nz);
+  Geom geo[kMaxLevels];
+  for (int k = 0; k <= kmax; k++) {
+    st = make_geom(nx, ny, nz, k, &geo[k]);
+    if (st) return st;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int E = region_edge, nry = (int)((ny + E - 1) / E);
+
+  // Groups: the leading small levels in two launches (up to 2^18 vertices,
+  // then the rest up to 2^22), every other level on its own; single levels
+  // with quad tiles are refined region by region.
+  Step steps[kMaxLevels];
+  int group_end[kMaxLevels];
+  for (int i = 0; i <= kmax; i++) {
+    steps[i].g = geo[kmax - i];
+    steps[i].slot = i;
+  }
+  for (int i = 0; i <= kmax;) {
+    int j = i + 1;
+    const int64_t cap = level_vertices(steps[i].g) <= ((int64_t)1 << 18) ? ((int64_t)1 << 18)
+                                                                          : kSmallLevel;
+    if (level_vertices(steps[i].g) <= kSmallLevel)
+      while (j <= kmax && j - i < kMaxFused && level_vertices(steps[j].g) <= cap) j++;
+    group_end[i] = j;
+    if (j == i + 1)
+      set_quad(&steps[i].g, quad_eligible(field, nx, steps[i].g.s, steps[i].g.dim));
+    i = j;
+  }
+  // scratch: compaction as usual, then the timeline's own
+  int64_t need_words = 0, need_chunks = 0, max_tiles = 1;
+  for (int i = 0; i <= kmax; i = group_end[i]) {
+    int64_t w, ch, lb;
+    launch_needs(&steps[i], group_end[i] - i, false, &w, &ch, &lb);
+    need_words = std::max(need_words, w);
+    need_chunks = std::max(need_chunks, ch);
+    if (group_end[i] == i + 1 && steps[i].g.quad) {
+      LevelDesc l{};
+      l.mx = (int)steps[i].g.mx;
+      l.my = (int)steps[i].g.my;
+      l.mz = (int)steps[i].g.mz;
+      plan_level_quad(l, std::min(kQuadZChunk, E / (int)steps[i].g.s));
+      max_tiles = std::max<int64_t>(max_tiles, l.ntiles);
+    }
+  }
+  st = ensure((void **)&c->bits, &c->bits_words, need_words * 8);
+  if (!st) st = ensure((void **)&c->counts, &c->counts_n, need_chunks * (int64_t)sizeof(int));
+  if (st) return st;
+  const int lf = feature_level(nx, ny, nz, kmax);
+  const int64_t nq = level_vertices(geo[lf]);
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t o_stamp = 0, o_rstamp = o_stamp + up(8 * (kMaxLevels + 2)),
+                o_left = o_rstamp + up(8 * (int64_t)(kmax + 1) * nregions),
+                o_rank = o_left + up(4 * (int64_t)nregions),
+                o_scr = o_rank + up(4 * (int64_t)nregions),
+                o_score = o_scr + up(4 * kRegionScratchInts(nregions)),
+                o_list = o_score + up(4 * (int64_t)nregions),
+                o_x = o_list + up(4 * max_tiles),
+                o_logit = o_x + (order_mode == 2 ? up(2 * kMlpIn * nq) : 0),
+                total = o_logit + (order_mode == 2 ? up(4 * nq) : 0);
+  st = ensure(&c->tl, &c->tl_bytes, total);
+  if (st) return st;
+  char *tb = static_cast<char *>(c->tl);
+  uint64_t *stamps = reinterpret_cast<uint64_t *>(tb + o_stamp);
+  uint64_t *rstamps = reinterpret_cast<uint64_t *>(tb + o_rstamp);
+  int *rank = reinterpret_cast<int *>(tb + o_rank);
+  if (order_mode != 2) {
+    std::vector<int> h(nregions);
+    for (int r = 0; r < nregions; r++) h[r] = order_mode == 1 ? rank_host[r] : r;
+    if (hipMemcpyAsync(rank, h.data(), sizeof(int) * nregions, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PCRIT_E_HIP;
+  }
+  if (hipMemsetAsync(rstamps, 0, 8 * (size_t)(kmax + 1) * nregions, s) != hipSuccess)
+    return PCRIT_E_HIP;
+
+  const unsigned gen = next_gen(c);
+  reset_kernel_marks(c);
+  int nstamp = 0;
+  int stamp_of_group[kMaxLevels];
+  if (launch_stamp(&stamps[nstamp++], s) != hipSuccess) return PCRIT_E_HIP;
+  bool ordered = order_mode != 2;
+  for (int i = 0; i <= kmax; i = group_end[i]) {
+    const int n = group_end[i] - i;
+    const bool regional = n == 1 && steps[i].g.quad;
+    RegionHooks rh;
+    if (regional) {
+      if (!ordered) {
+        // learned order: features of level lf, logits, region scores, ranks
+        uint16_t *X = reinterpret_cast<uint16_t *>(tb + o_x);
+        float *logit = reinterpret_cast<float *>(tb + o_logit);
+        float *score = reinterpret_cast<float *>(tb + o_score);
+        const Geom &gf = geo[lf];
+        if (launch_mlp_features(field, nx, ny, nz, (int)gf.s, (int)gf.mx, (int)gf.my,
+                                (int)gf.mz, resolution_feature(nx, ny, nz, lf), X,
+                                s) != hipSuccess ||
+            launch_mlp_forward(mlp_params, X, nq, logit, s) != hipSuccess ||
+            launch_region_scores(logit, (int)gf.s, (int)gf.mx, (int)gf.my, (int)gf.mz, E, nry,
+                                 nregions, score, s) != hipSuccess ||
+            launch_region_rank(score, nregions, rank, s) != hipSuccess)
+          return PCRIT_E_HIP;
+        ordered = true;
+      }
+      rh.E = E;
+      rh.nry = nry;
+      rh.nregions = nregions;
+      rh.rank = rank;
+      rh.tile_list = reinterpret_cast<int *>(tb + o_list);
+      rh.scratch = reinterpret_cast<int *>(tb + o_scr);
+      rh.left = reinterpret_cast<unsigned *>(tb + o_left);
+      rh.stamp = rstamps + (int64_t)i * nregions;
+    }
+    st = enqueue_group(c, s, field, &steps[i], n, codes, crit, nullptr, crit_capacity, nullptr,
+                       gen, i + n > kmax, c->bits, c->counts, nullptr, 0,
+                       regional ? &rh : nullptr);
+    if (st) return st;
+    stamp_of_group[i] = nstamp;
+    if (launch_stamp(&stamps[nstamp++], s) != hipSuccess) return PCRIT_E_HIP;
+  }
+  std::vector<uint64_t> hs(nstamp), hr((size_t)(kmax + 1) * nregions);
+  if (order_mode == 2 && rank_host) {
+    if (!ordered) {
+      for (int r = 0; r < nregions; r++) rank_host[r] = r;
+    } else if (hipMemcpyAsync(rank_host, rank, sizeof(int) * nregions, hipMemcpyDeviceToHost,
+                              s) != hipSuccess) {
+      return PCRIT_E_HIP;
+    }
+  }
+  if (hipMemcpyAsync(hs.data(), stamps, 8 * (size_t)nstamp, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(hr.data(), rstamps, 8 * hr.size(), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      read_status(c, s))
+    return PCRIT_E_HIP;
+  // GPU clock: 100 MHz
+  auto ms = [&](uint64_t t) { return (double)(int64_t)(t - hs[0]) * 1e-5; };
+  for (int i = 0; i <= kmax; i = group_end[i]) {
+    const double done = ms(hs[stamp_of_group[i]]);
+    const bool regional = group_end[i] == i + 1 && steps[i].g.quad;
+    for (int j = i; j < group_end[i]; j++) {
+      level_ms_host[j] = done;
+      for (int r = 0; r < nregions; r++) {
+        const uint64_t t = hr[(size_t)j * nregions + r];
+        region_ms_host[(size_t)j * nregions + r] = regional && t ? ms(t) : done;
+      }
+    }
+  }
+  for (int i = 0; i <= kmax + 1; i++) level_offsets_host[i] = c->h_base[i];
+  if (c->h_flags[0] == gen) return PCRIT_E_NAN;
+  return c->h_base[kmax + 1] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
 
 }  // extern "C"

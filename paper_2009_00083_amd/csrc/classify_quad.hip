@@ -27,6 +27,8 @@
 // The critical bits of a row leave as the level's 64-bit bitmask words
 // (bit b = column 64 w + b): each lane shifts its four bits to its place in
 // a word and sixteen lanes OR them together with DPP row shifts.
+#include <algorithm>
+
 #include "device_util.h"
 #include "pcrit_internal.h"
 
@@ -441,7 +443,9 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
   }
 }
 
-template <int R, int SX>
+// LISTED: tiles from the region-ordered per-XCD lists (QuadArgs::tile_list)
+// instead of a grid-stride walk over the level.
+template <int R, int SX, bool LISTED>
 __global__ __launch_bounds__(64 * kQuadBlockWaves)
 __attribute__((amdgpu_waves_per_eu(SX == 1 ? kQuadWavesPerSimd : kQuadWavesPerSimd - 1)))
 void classify3d_quad_kernel(QuadArgs a) {
@@ -456,8 +460,25 @@ void classify3d_quad_kernel(QuadArgs a) {
   }
   __syncthreads();
   bool nan_seen = false;
+  // Tiles: grid-stride over the level, or (region order) this XCD's list,
+  // one tile per increment of its counter.
+  const int x = (int)blockIdx.x % kXcds;
+  const int beg = LISTED ? a.xcd_off[x] : 0, nlist = LISTED ? a.xcd_off[x + 1] - beg : 0;
   const int nwaves = (int)gridDim.x * NW;
-  for (int t = xcd_block_id() * NW + w; t < a.lv.ntiles; t += nwaves) {
+  int t0 = xcd_block_id() * NW + w;
+  for (;;) {
+    int t;
+    if (LISTED) {
+      int i = 0;
+      if (lane == 0) i = atomicAdd(&a.queue[x], 1);
+      i = __builtin_amdgcn_readfirstlane(i);
+      if (i >= nlist) break;
+      t = a.tile_list[beg + i];
+    } else {
+      if (t0 >= a.lv.ntiles) break;
+      t = t0;
+      t0 += nwaves;
+    }
     const TilePos p = tile_pos(a.lv, t);
     const int y0 = p.ty * R, z0 = p.zc * a.lv.zchunk;
     const bool inner = y0 >= 1 && y0 + R <= a.lv.my - 1 && z0 >= 1 &&
@@ -466,25 +487,39 @@ void classify3d_quad_kernel(QuadArgs a) {
       quad_tile<R, SX, false>(a, t, lane, slut, nan_seen);
     else
       quad_tile<R, SX, true>(a, t, lane, slut, nan_seen);
+    if (LISTED) {
+      // the region's last tile stamps the clock once this tile's stores
+      // are complete
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) {
+        const int r = ((p.zc * a.lv.zchunk * SX) / a.region_edge) * a.nry +
+                      (p.ty * R * SX) / a.region_edge;
+        if (atomicSub(&a.region_left[r], 1u) == 1u)
+          a.region_stamp[r] = __builtin_amdgcn_s_memrealtime();
+      }
+    }
   }
   if (wave_ballot(nan_seen) && lane == 0) *a.nan_flag = a.gen;
 }
 
 // Quad tiles per wave of a launch (the kernel strides over tiles by the
 // grid's wave count).
-constexpr int kQuadTileRounds = 2;
+#ifndef PCRIT_QUAD_TILE_ROUNDS
+#define PCRIT_QUAD_TILE_ROUNDS 2
+#endif
+constexpr int kQuadTileRounds = PCRIT_QUAD_TILE_ROUNDS;
 // Tile depth: the deepest multiple of 2 up to kQuadZChunk that still gives
 // kQuadWantTiles tiles.
 constexpr int64_t kQuadWantTiles = 4096;
 
 }  // namespace
 
-void plan_level_quad(LevelDesc &l) {
+void plan_level_quad(LevelDesc &l, int zchunk) {
   l.ntx = (l.mx + kQuadCols - 1) / kQuadCols;
   l.nty = (l.my + kQuadRows - 1) / kQuadRows;
   int d = kQuadZChunk;
   while (d > 2 && (int64_t)l.ntx * l.nty * ((l.mz + d - 1) / d) < kQuadWantTiles) d -= 2;
-  l.zchunk = d;
+  l.zchunk = zchunk > 0 ? zchunk : d;
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor((uint32_t)l.nty, &l.nty_mul, &l.nty_shift);
@@ -499,14 +534,23 @@ bool quad_eligible(const float *field, int64_t nx, int64_t s, int dim) {
 
 hipError_t launch_classify_quad(const QuadArgs &a, hipStream_t st) {
   const int64_t per_block = (int64_t)kQuadBlockWaves * kQuadTileRounds;
-  const int g = (int)((a.lv.ntiles + per_block - 1) / per_block);
+  int g = (int)((a.lv.ntiles + per_block - 1) / per_block);
+  // region order: every XCD drains its own list, so each needs workgroups
+  // (a multiple of kXcds); beyond what the chip holds at once more add
+  // nothing
+  if (a.tile_list) g = std::min((g + kXcds - 1) / kXcds * kXcds, 2048);
   const dim3 grid((unsigned)(g > 0 ? g : 1)), block(64 * kQuadBlockWaves);
-  if (a.lv.sx == 1)
-    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1>), grid, block, 0, st, a);
-  else if (a.lv.sx == 2)
-    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2>), grid, block, 0, st, a);
-  else
-    return hipErrorInvalidValue;
+  if (a.lv.sx != 1 && a.lv.sx != 2) return hipErrorInvalidValue;
+  if (a.tile_list) {
+    if (a.lv.sx == 1)
+      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1, true>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, true>), grid, block, 0, st, a);
+  } else if (a.lv.sx == 1) {
+    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1, false>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, false>), grid, block, 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -19,18 +19,23 @@ inline unsigned char point_type(unsigned char code) {
   return 3;
 }
 
-}  // namespace
-
-extern "C" int pcrit_preview_f1(int64_t nx, int64_t ny, int64_t nz, int level,
-                                const uint32_t *preview,
-                                const uint8_t *preview_codes, int64_t n_preview,
-                                const uint32_t *exact,
-                                const uint8_t *exact_codes, int64_t n_exact,
-                                double *f1, int64_t *matches_out) {
+// Preview points carry their own level (tolerance 2^level); `levels` may be
+// null, then every point has level `level`.
+int preview_f1(int64_t nx, int64_t ny, int64_t nz, int level, const uint8_t *levels,
+               const uint32_t *preview, const uint8_t *preview_codes, int64_t n_preview,
+               const uint32_t *exact, const uint8_t *exact_codes, int64_t n_exact,
+               double *f1, int64_t *matches_out) {
   if (!f1 || n_preview < 0 || n_exact < 0 || level < 0 || level > 30 ||
       (n_preview && (!preview || !preview_codes)) ||
       (n_exact && (!exact || !exact_codes)))
     return PCRIT_E_ARG;
+  if (levels) {
+    level = 0;
+    for (int64_t i = 0; i < n_preview; i++) {
+      if (levels[i] > 30) return PCRIT_E_ARG;
+      level = std::max(level, (int)levels[i]);
+    }
+  }
   if (nx < 2 || ny < 2 || nz < 1) return PCRIT_E_DIMS;
   const int64_t n = nx * ny * nz;
   if (n > 4294967295ll) return PCRIT_E_DIMS;
@@ -59,6 +64,7 @@ extern "C" int pcrit_preview_f1(int64_t nx, int64_t ny, int64_t nz, int level,
       const int64_t p = preview[i];
       const unsigned char t = point_type(preview_codes[i]);
       if (!t) continue;
+      if (levels && d > ((int64_t)1 << levels[i])) continue;
       const int64_t px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
       bool found = false;
       const int64_t dz0 = -std::min(d, dzmax), dz1 = std::min(d, dzmax);
@@ -104,4 +110,28 @@ extern "C" int pcrit_preview_f1(int64_t nx, int64_t ny, int64_t nz, int level,
   *f1 = 2.0 * (double)matches / (double)(n_preview + n_exact);
   if (matches_out) *matches_out = matches;
   return PCRIT_OK;
+}
+
+}  // namespace
+
+extern "C" int pcrit_preview_f1(int64_t nx, int64_t ny, int64_t nz, int level,
+                                const uint32_t *preview,
+                                const uint8_t *preview_codes, int64_t n_preview,
+                                const uint32_t *exact,
+                                const uint8_t *exact_codes, int64_t n_exact,
+                                double *f1, int64_t *matches_out) {
+  return preview_f1(nx, ny, nz, level, nullptr, preview, preview_codes, n_preview, exact,
+                    exact_codes, n_exact, f1, matches_out);
+}
+
+extern "C" int pcrit_preview_f1_levels(int64_t nx, int64_t ny, int64_t nz,
+                                       const uint32_t *preview,
+                                       const uint8_t *preview_codes,
+                                       const uint8_t *preview_levels_host, int64_t n_preview,
+                                       const uint32_t *exact, const uint8_t *exact_codes,
+                                       int64_t n_exact, double *f1, int64_t *matches_out) {
+  if (n_preview && !preview_levels_host) return PCRIT_E_ARG;
+  return preview_f1(nx, ny, nz, 0, preview_levels_host ? preview_levels_host : (const uint8_t *)"",
+                    preview, preview_codes, n_preview, exact, exact_codes, n_exact, f1,
+                    matches_out);
 }

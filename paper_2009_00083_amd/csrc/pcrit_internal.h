@@ -233,10 +233,22 @@ struct QuadArgs {
   LevelDesc lv;
   unsigned *nan_flag;
   unsigned gen;
+  // Region timeline (null unless requested): the waves of XCD x take the
+  // tiles of tile_list[xcd_off[x] ..] in order, one at a time, through the
+  // counter queue[x] (zero at launch); a tile belongs to region (rz, ry) of
+  // edge region_edge (full-resolution rows and planes); the wave that
+  // finishes a region's last tile (region_left counts down) stores the GPU
+  // clock in region_stamp.
+  const int *tile_list;
+  const int *xcd_off;
+  int *queue;
+  unsigned *region_left;
+  uint64_t *region_stamp;
+  int region_edge, nry;
 };
 // Level geometry of a quad launch; whether a level can take one (stride 1
 // or 2, 16-byte aligned rows).
-void plan_level_quad(LevelDesc &l);
+void plan_level_quad(LevelDesc &l, int zchunk = 0);  // zchunk 0: chosen by size
 bool quad_eligible(const float *field, int64_t nx, int64_t s, int dim);
 hipError_t launch_classify_quad(const QuadArgs &a, hipStream_t st);
 
@@ -245,5 +257,47 @@ hipError_t launch_classify_quad(const QuadArgs &a, hipStream_t st);
 constexpr int64_t kNoAllocScratchBytes = int64_t(32) << 20;
 hipError_t noalloc_scratch_init(int device);  // with `device` current
 void *noalloc_scratch(int device);            // null before the init
+
+// Learned refinement order (learned.hip).  MLP parameters, FP32, in this
+// order: W1 [32 inputs][64], b1 [64], W2 [64][64], b2 [64], w3 [64], b3.
+constexpr int kMlpIn = 32, kMlpHidden = 64;
+constexpr int kMlpOffW1 = 0;
+constexpr int kMlpOffB1 = kMlpOffW1 + kMlpIn * kMlpHidden;
+constexpr int kMlpOffW2 = kMlpOffB1 + kMlpHidden;
+constexpr int kMlpOffB2 = kMlpOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kMlpOffW3 = kMlpOffB2 + kMlpHidden;
+constexpr int kMlpOffB3 = kMlpOffW3 + kMlpHidden;
+constexpr int kMlpParams = kMlpOffB3 + 1;
+constexpr int kMaxRegions = 1024;
+hipError_t launch_mlp_forward(const float *params, const uint16_t *X, int64_t n, float *logits,
+                              hipStream_t st);
+hipError_t launch_mlp_backward(const float *params, const uint16_t *X, const uint8_t *y,
+                               int64_t n, float *grad, float *loss, hipStream_t st);
+hipError_t launch_mlp_adam(float *params, const float *grad, float *m, float *v, float lr,
+                           int t, hipStream_t st);
+hipError_t launch_mlp_features(const float *f, int64_t nx, int64_t ny, int64_t nz, int s,
+                               int mx, int my, int mz, float res, uint16_t *X, hipStream_t st);
+hipError_t launch_mlp_labels(const uint8_t *codes, int64_t nx, int64_t ny, int64_t nz, int s,
+                             int mx, int my, int mz, uint8_t *label, hipStream_t st);
+hipError_t launch_region_scores(const float *logits, int s, int mx, int my, int mz, int E,
+                                int nry, int nregions, float *scores, hipStream_t st);
+// Region ranks from scores (descending score, then ascending region id).
+hipError_t launch_region_rank(const float *scores, int nregions, int *rank, hipStream_t st);
+// Tile lists of a quad level for its region-ordered launch, and each
+// region's tile count in region_left.  The tiles of every region are split
+// into kXcds contiguous parts; list x (at xcd_off[x] .. xcd_off[x + 1] of
+// tile_list) holds part x of every region, regions in rank order, and is
+// drained in that order by the workgroups of XCD x (blockIdx.x % kXcds)
+// through the counter queue[x].  scratch: kRegionScratchInts(nregions) ints;
+// xcd_off and queue point into it (region_xcd_off, region_queue).
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int64_t kRegionScratchInts(int nregions) { return (int64_t)kXcds * nregions + 32; }
+__host__ __device__ inline int *region_xcd_off(int *scratch, int nregions) { return scratch + kXcds * nregions; }
+__host__ __device__ inline int *region_queue(int *scratch, int nregions) { return scratch + kXcds * nregions + 16; }
+hipError_t launch_region_tiles(const LevelDesc &l, int R, int s, int E, int nry, int nregions,
+                               const int *rank, int *tile_list, unsigned *region_left,
+                               int *scratch, hipStream_t st);
+// Stores the GPU clock (100 MHz) in *out.
+hipError_t launch_stamp(uint64_t *out, hipStream_t st);
 
 }  // namespace pcrit

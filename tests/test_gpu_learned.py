@@ -1,0 +1,225 @@
+"""GPU parity of the learned refinement order: the network's inputs and
+targets bit for bit, its forward and backward passes and the Adam step
+against the oracle (``oracle/learned.py``), training, and the region
+timeline (any order gives the lists and codes of the plain progressive call
+and of the oracle; the order is honoured; the learned order is the oracle's
+ranking of the oracle's scores)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle
+from oracle import learned as OL
+import paper_2009_00083_amd as pc
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    return pc.Context(0)
+
+
+def _bits(t):
+    return t.cpu().view(torch.int16).numpy().view(np.uint16)
+
+
+FEATURE_CASES = [((33, 40, 68), 1), ((33, 40, 68), 2), ((17, 9, 130), 1), ((64, 64, 64), 3),
+                 ((5, 6, 7), 1)]
+
+
+@pytest.mark.parametrize("shape,level", FEATURE_CASES)
+def test_features_bit_exact(ctx, dev, shape, level):
+    f = fieldgen.gaussian_field(shape, 7 + level, 6, noise=("uniform", 1e-3))
+    f[0, 0, :3] = f[0, 0, 0]  # equal samples next to each other
+    log("features", shape, level)
+    X = pc.mlp_features(torch.from_numpy(f).to(dev), level, ctx=ctx)
+    torch.cuda.synchronize()
+    got = OL.bf16_bits_to_float(_bits(X)).reshape(-1, 32)
+    ref = OL.features(f, level)
+    bad = np.flatnonzero((got != ref).any(1))
+    assert bad.size == 0, f"{bad.size} rows differ, first {bad[:4]}"
+
+
+def test_features_constant_field(ctx, dev):
+    f = np.full((9, 10, 12), 2.5, np.float32)
+    X = pc.mlp_features(torch.from_numpy(f).to(dev), 1, ctx=ctx)
+    got = OL.bf16_bits_to_float(_bits(X)).reshape(-1, 32)
+    assert np.array_equal(got, OL.features(f, 1))
+    assert np.all(got[:, :27] == 0)
+
+
+@pytest.mark.parametrize("shape", [(33, 40, 68), (20, 17, 9)])
+def test_labels_bit_exact(ctx, dev, shape):
+    f = fieldgen.gaussian_field(shape, 3, 5, noise=("uniform", 1e-2))
+    ref_codes = oracle.classify(f).codes
+    ct = torch.from_numpy(ref_codes).to(dev)
+    for level in range(1, pc.max_level(shape) + 1):
+        got = pc.mlp_labels(ct, level, ctx=ctx).cpu().numpy()
+        assert np.array_equal(got, OL.labels(ref_codes, level)), level
+
+
+def _inputs(dev, n, seed):
+    """Inputs of real fields (rows of features) with a ragged count."""
+    f = fieldgen.gaussian_field((40, 40, 40), seed, 8, noise=("uniform", 1e-3))
+    X = OL.features(f, 1)
+    rng = np.random.default_rng(seed)
+    X = X[rng.integers(0, X.shape[0], n)]
+    bits = (X.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    Xt = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16).reshape(n, 32)
+    return X, Xt
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 1000, 4099])
+def test_forward_matches_oracle(ctx, dev, n):
+    rng = np.random.default_rng(n)
+    p = (rng.standard_normal(pc.MLP_PARAMS) * 0.3).astype(np.float32)
+    X, Xt = _inputs(dev, n, n)
+    z = pc.mlp_forward(torch.from_numpy(p).to(dev), Xt, ctx=ctx).cpu().numpy()
+    ref, _ = OL.forward(p, X)
+    err = np.abs(z - ref)
+    log("forward n", n, "max err", err.max(), "median", np.median(err))
+    # FP32 accumulation; a BF16 rounding of h1 may go the other way
+    assert np.all(err <= 2e-3 * (1 + np.abs(ref)))
+    assert np.median(err) <= 1e-4 * (1 + np.median(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n", [1, 31, 33, 5000])
+def test_backward_matches_oracle(ctx, dev, n):
+    rng = np.random.default_rng(100 + n)
+    p = (rng.standard_normal(pc.MLP_PARAMS) * 0.3).astype(np.float32)
+    X, Xt = _inputs(dev, n, 50 + n)
+    y = rng.integers(0, 2, n).astype(np.uint8)
+    g, loss = pc.mlp_backward(torch.from_numpy(p).to(dev), Xt, torch.from_numpy(y).to(dev),
+                              ctx=ctx)
+    g = g.cpu().numpy().astype(np.float64)
+    ref = OL.backward(p, X, y)
+    lref = OL.loss_sum(p, X, y)
+    assert abs(float(loss.item()) - lref) <= 1e-4 * abs(lref) + 1e-5
+    blocks = {"W1": (OL.OFF_W1, OL.OFF_B1), "b1": (OL.OFF_B1, OL.OFF_W2),
+              "W2": (OL.OFF_W2, OL.OFF_B2), "b2": (OL.OFF_B2, OL.OFF_W3),
+              "w3": (OL.OFF_W3, OL.OFF_B3), "b3": (OL.OFF_B3, OL.N_PARAMS)}
+    for name, (lo, hi) in blocks.items():
+        a, b = g[lo:hi], ref[lo:hi]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        log("backward n", n, name, "rel err", rel)
+        # the products take BF16 operands: about 2^-9 per rounded factor
+        assert rel <= 1.5e-2, name
+
+
+def test_adam_matches_oracle(ctx, dev):
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal(pc.MLP_PARAMS).astype(np.float32)
+    pt = torch.from_numpy(p).to(dev)
+    m = torch.zeros_like(pt)
+    v = torch.zeros_like(pt)
+    rp, rm, rv = p.astype(np.float64), np.zeros(pc.MLP_PARAMS), np.zeros(pc.MLP_PARAMS)
+    for t in range(1, 4):
+        g = (rng.standard_normal(pc.MLP_PARAMS) * 10.0 ** rng.integers(-3, 1)).astype(np.float32)
+        pc.mlp_adam(pt, torch.from_numpy(g).to(dev), m, v, 1e-2, t, ctx=ctx)
+        rp, rm, rv = OL.adam_step(rp, g, rm, rv, 1e-2, t)
+    assert np.allclose(pt.cpu().numpy(), rp, rtol=1e-5, atol=1e-6)
+    assert np.allclose(m.cpu().numpy(), rm, rtol=1e-5, atol=1e-9)
+    assert np.allclose(v.cpu().numpy(), rv, rtol=1e-4, atol=1e-12)
+
+
+def test_training_lowers_loss(ctx, dev):
+    f = fieldgen.config_field("gsin256", shape=(128, 128, 128))
+    ts = pc.learned_order.training_set(torch.from_numpy(f).to(dev), ctx=ctx)
+    assert ts.level == pc.mlp_feature_level(f.shape)
+    params = pc.learned_order.init_params(0, dev)
+    losses = pc.learned_order.train(params, [ts], steps=150, lr=3e-3, ctx=ctx)
+    log("training loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.8 * losses[0]
+    # the loss the kernels report is the oracle's on the same parameters
+    X = OL.bf16_bits_to_float(_bits(ts.X)).reshape(-1, 32)
+    y = ts.y.cpu().numpy()
+    g, loss = pc.mlp_backward(params, ts.X, ts.y, ctx=ctx)
+    lref = OL.loss_sum(params.cpu().numpy(), X, y)
+    assert abs(loss.item() - lref) <= 1e-4 * lref
+
+
+def _check_timeline(f, t, ref_lists):
+    assert t.status == 0
+    crit = t.crit.cpu().numpy().view(np.uint32)
+    for i, k in enumerate(t.levels):
+        assert np.array_equal(crit[t.offsets[i]:t.offsets[i + 1]], ref_lists[k]), k
+    lms = t.level_ms
+    assert np.all(np.diff(lms) >= 0) and lms[0] >= 0
+    assert np.all(t.region_ms <= lms[:, None] + 1e-9)
+    assert np.all(t.region_ms >= 0)
+
+
+@pytest.mark.parametrize("shape,edge", [((130, 132, 256), 32), ((96, 100, 68), 64),
+                                        ((64, 64, 64), 32)])
+def test_timeline_any_order_same_result(ctx, dev, shape, edge):
+    f = fieldgen.gaussian_field(shape, 31, 12, noise=("uniform", 1e-3))
+    ft = torch.from_numpy(f).to(dev)
+    base = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    refs = {k: oracle.classify(f, level=k).crit for k in base.levels}
+    nreg = pc.region_count(shape, edge)
+    rng = np.random.default_rng(sum(shape))
+    orders = [None, np.arange(nreg)[::-1].copy(), rng.permutation(nreg), rng.permutation(nreg)]
+    for order in orders:
+        log("timeline", shape, edge, "order", None if order is None else order[:6])
+        t = pc.progressive_timeline(ft, edge, order=order, ctx=ctx)
+        _check_timeline(f, t, refs)
+        assert torch.equal(t.codes, base.codes)
+        assert np.array_equal(t.offsets, base.offsets)
+
+
+def test_timeline_honours_order(ctx, dev):
+    """At 512 x 256 x 256 the level-0 pass takes many waves of work: the
+    regions ranked first finish before those ranked last."""
+    shape = (256, 256, 512)
+    f = fieldgen.gaussian_field(shape, 5, 32, noise=("uniform", 1e-3), device="cuda")
+    ft = torch.from_numpy(f).to(dev)
+    nreg = pc.region_count(shape, 32)
+    rank = np.random.default_rng(2).permutation(nreg).astype(np.int32)
+    t = pc.progressive_timeline(ft, 32, order=rank, ctx=ctx)
+    assert t.status == 0
+    i0 = t.levels.index(0)
+    by_rank = t.region_ms[i0][np.argsort(rank)]
+    q = nreg // 4
+    log("level-0 region stamps by rank quartile",
+        [float(np.median(by_rank[a * q:(a + 1) * q])) for a in range(4)])
+    assert np.median(by_rank[:q]) < np.median(by_rank[-q:])
+    assert by_rank[0] < by_rank[-1]
+
+
+def test_timeline_learned_order(ctx, dev):
+    """The learned order ranks the regions by the oracle's scores (the
+    oracle's network on the oracle's inputs), within the FP32 rounding of the
+    sums; the result is that of the plain call."""
+    shape = (128, 96, 132)
+    f = fieldgen.gaussian_field(shape, 8, 16, noise=("uniform", 1e-3))
+    ft = torch.from_numpy(f).to(dev)
+    params = pc.learned_order.init_params(3, dev)
+    edge = 32
+    t = pc.progressive_timeline(ft, edge, params=params, ctx=ctx)
+    base = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    refs = {k: oracle.classify(f, level=k).crit for k in base.levels}
+    _check_timeline(f, t, refs)
+    lf = pc.mlp_feature_level(shape)
+    z, _ = OL.forward(params.cpu().numpy(), OL.features(f, lf))
+    sc = OL.region_scores(z, shape, lf, edge)
+    rank = t.rank
+    assert sorted(rank.tolist()) == list(range(len(sc)))
+    order = np.argsort(rank)
+    tol = 1e-3 * (1 + np.abs(sc).max())
+    assert np.all(sc[order][:-1] >= sc[order][1:] - tol)
