@@ -1,17 +1,24 @@
 """Benchmark: progressive critical-point classification of a 512^3 field.
 
 One step = one pass of the whole hot path: every level of the hierarchy,
-coarse (2^3) to fine (512^3), each level classified (new vertices, plus old
-vertices whose polarity changed) and compacted into its ascending critical
-list.  The field is resident in HBM before the timed region.
+coarse (2^3) to fine (512^3), every vertex of each level classified and the
+level compacted into its ascending critical list.  The field is resident in
+HBM before the timed region.
 
 Prints one JSON line.  value = vertices of all levels / ms_per_step, in
 Gvertices/s, with the steps enqueued back to back through the asynchronous
 entry point; ms_per_step_sync is the same loop through the synchronous one
-(the host waits for every step).  Extra keys: time_to_exact_ms (first enqueue to level-0
-completion, stream events), preview F1 at 10 % of that time, the direct
-level-0 rate, per-level rates, the roofline of the dominant kernel, and the
-CPU oracle's rate on a bounded sample of the same workload.
+(the host waits for every step).  Extra keys: time_to_exact_ms (start of
+the step's first kernel to level-0 completion, stream events, with the
+step's kernels already queued); "preview": F1 of the preview
+against the exact list at 10, 25, 50, 75 and 90 % of the plain call's time
+to exact, for the
+plain level order, for region-by-region refinement in region id order and
+in the learned order (the order network trained, untimed, on held-out
+fields), on this field and on the smooth recipe at 512^3; the direct level-0
+rate; per-level rates; the roofline of the dominant kernel; and the CPU
+oracle's rate on bounded samples of the same workload (all threads of this
+process's share, and one thread).
 """
 import argparse
 import hashlib
@@ -30,6 +37,17 @@ WORKLOAD = "noisy512"
 PMC_FILE = os.path.join(ROOT, "profiles", "classify3d_quad_level0_noisy512_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2009_00083_amd", "csrc", n)
                   for n in ("classify_quad.hip", "device_util.h", "pcrit_internal.h")]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def kernel_source_hash():
@@ -61,12 +79,127 @@ def measured_traffic():
         return None
 
 
+PREVIEW_FRACS = (0.10, 0.25, 0.50, 0.75, 0.90)
+# evaluation fields (the bench field and the smooth gsin recipe at 512^3)
+# and the held-out fields of the same recipes the order network trains on
+EVAL_FIELDS = {"noisy512": ("noisy512", None), "gsin512": ("gsin256", None)}
+TRAIN_FIELDS = [("noisy512", 13), ("gsin256", 12)]
+
+
+def recipe_field(recipe, seed=None, shape=(512, 512, 512)):
+    import fieldgen
+    kw = dict(fieldgen.CONFIGS[recipe])
+    kw["shape"] = tuple(shape)
+    if seed is not None:
+        kw["seed"] = seed
+    return fieldgen.gaussian_field(device="cuda", **kw)
+
+
+def train_order_network(pc, ctx, dev, steps=3000):
+    """Trains the refinement-order network on held-out fields of both
+    recipes (untimed); returns (params, first and last mean loss)."""
+    import torch
+    sets = []
+    for recipe, seed in TRAIN_FIELDS:
+        ft = torch.from_numpy(recipe_field(recipe, seed)).to(dev)
+        sets.append(pc.learned_order.training_set(ft, ctx=ctx))
+        del ft
+    params = pc.learned_order.init_params(0, dev)
+    losses = pc.learned_order.train(params, sets, steps=steps, lr=1e-2, ctx=ctx)
+    return params, sets[0].level, losses
+
+
+def _region_of(points, shape, edge):
+    nz, ny, nx = shape
+    nry = -(-ny // edge)
+    p = points.astype(np.int64)
+    return ((p // (nx * ny)) // edge) * nry + ((p // nx) % ny) // edge
+
+
+def preview_quality(pc, ctx, ft, params, reps=5, edge=64):
+    """Preview F1 against the exact list at PREVIEW_FRACS of the plain
+    call's time to exact (one clock for every mode): 'plain' shows the
+    finest level whose list is complete; 'regional' (regions in id order),
+    'learned' (regions by the network's scores) and 'ideal' (regions by
+    their exact critical counts: a bound no real order reaches) show each
+    region at the finest level finished there.  None where no preview
+    exists yet."""
+    shape = tuple(ft.shape)
+    pr = pc.progressive(ft, ctx=ctx, with_crit_codes=True)
+    levels = pr.levels
+    lists = {k: pr.level_list(k).cpu().numpy().view(np.uint32) for k in levels}
+    lcodes = {k: pr.level_codes(k).cpu().numpy() for k in levels}
+    regs = {k: _region_of(lists[k], shape, edge) for k in levels}
+    exact, exact_c = lists[0], lcodes[0]
+    cache = {}
+
+    def f1_levels(chosen):
+        """chosen[r] = level index shown for region r (-1: none)."""
+        key = chosen.tobytes()
+        if key in cache:
+            return cache[key]
+        pts, cds, lvs = [], [], []
+        for i, k in enumerate(levels):
+            m = chosen[regs[k]] == i
+            if m.any():
+                pts.append(lists[k][m])
+                cds.append(lcodes[k][m])
+                lvs.append(np.full(int(m.sum()), k, np.uint8))
+        if not pts:
+            cache[key] = None
+            return None
+        f1, _ = pc.preview_f1_levels(shape, np.concatenate(pts), np.concatenate(cds),
+                                     np.concatenate(lvs), exact, exact_c)
+        cache[key] = round(float(f1), 4)
+        return cache[key]
+
+    nreg = pc.region_count(shape, edge)
+    out = {}
+    # plain: level-granular completion times of the plain progressive call
+    lvl = np.median(np.array([pc.progressive(ft, ctx=ctx, level_times=True).level_ms
+                              for _ in range(reps)]), axis=0)
+    t_ex = clock = float(lvl[-1])
+    curve = {}
+    for fr in PREVIEW_FRACS:
+        done = [i for i in range(len(levels)) if lvl[i] <= fr * clock]
+        curve[f"{int(fr * 100)}%"] = (f1_levels(np.full(nreg, done[-1], np.int64))
+                                      if done else None)
+    out["plain"] = {"f1": curve, "time_to_exact_ms": round(t_ex, 4),
+                    "time_to_first_preview_ms": round(float(lvl[0]), 4)}
+    # an upper bound for any order: regions by their exact number of
+    # level-0 critical points (known only once the exact pass has run)
+    counts = np.bincount(regs[0], minlength=nreg)
+    ideal_rank = np.empty(nreg, np.int32)
+    ideal_rank[np.argsort(-counts, kind="stable")] = np.arange(nreg, dtype=np.int32)
+    for mode in ("regional", "learned", "ideal"):
+        runs = [pc.progressive_timeline(ft, edge, params=params if mode == "learned" else None,
+                                        order=ideal_rank if mode == "ideal" else None,
+                                        ctx=ctx) for _ in range(reps)]
+        for t in runs:
+            assert t.status == 0 and np.array_equal(t.offsets, pr.offsets)
+        lms = np.median(np.array([t.level_ms for t in runs]), axis=0)
+        rms = np.median(np.array([t.region_ms for t in runs]), axis=0)
+        t_ex = float(lms[-1])
+        curve = {}
+        for fr in PREVIEW_FRACS:
+            done = rms <= fr * clock  # [level index, region]
+            idx = np.arange(len(levels))[:, None]
+            chosen = np.where(done, idx, -1).max(axis=0)
+            curve[f"{int(fr * 100)}%"] = f1_levels(chosen)
+        out[mode] = {"f1": curve, "time_to_exact_ms": round(t_ex, 4),
+                     "time_to_first_preview_ms": round(float(lms[0]), 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-preview", action="store_true",
+                    help="skip the preview-quality passes (and the order "
+                         "network's training)")
     ap.add_argument("--cpu-planes", type=int, default=512,
                     help="level-0 z-planes of the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -141,7 +274,8 @@ def main():
     assert np.array_equal(offs_dev.cpu().numpy(), r.offsets)
 
     # region T: the same steps with a completion event per launch; time to
-    # exact = first kernel to level-0 completion (stream events)
+    # exact = first kernel to level-0 completion (stream events; the call
+    # queues its kernels behind a short GPU wait before the start event)
     lvl_ms = []
     for _ in range(args.steps):
         lvl_ms.append(step(level_times=True).level_ms.copy())
@@ -194,22 +328,22 @@ def main():
     achieved = alg_bytes / (k0_ms * 1e-3) / 1e9
     traffic = measured_traffic()
 
-    # preview F1 at 10 % of time-to-exact (lists are deterministic, so take
-    # them from one more untimed pass that also returns the codes)
-    pr = pc.progressive(ft, ctx=ctx, with_crit_codes=True)
     med_lvl = np.median(lvl_ms, axis=0)
-    budget = 0.1 * t_exact
-    done = [i for i in range(len(levels)) if med_lvl[i] <= budget]
-    exact = pr.level_list(0).cpu().numpy().view(np.uint32)
-    exact_c = pr.level_codes(0).cpu().numpy()
-    if done:
-        i = done[-1]
-        kprev = levels[i]
-        prev = pr.level_list(kprev).cpu().numpy().view(np.uint32)
-        prev_c = pr.level_codes(kprev).cpu().numpy()
-        f1, _ = pc.preview_f1(shape, kprev, prev, prev_c, exact, exact_c)
-    else:
-        kprev, f1 = None, 0.0
+
+    # preview quality (untimed passes): plain level order, regions in id
+    # order, regions in the learned order, on this field and on the smooth
+    # recipe at 512^3; the order network trains first on held-out fields
+    previews = {}
+    if not args.no_preview:
+        params, flevel, losses = train_order_network(pc, ctx, dev)
+        previews["order_network"] = {
+            "trained_on": [f"{r} recipe, seed {sd}, 512^3" for r, sd in TRAIN_FIELDS],
+            "scoring_level": flevel, "adam_steps": len(losses),
+            "mean_loss_first": round(losses[0], 4), "mean_loss_last": round(losses[-1], 4)}
+        for name, (recipe, seed) in EVAL_FIELDS.items():
+            fe = ft if name == WORKLOAD else torch.from_numpy(recipe_field(recipe, seed)).to(dev)
+            previews[name] = preview_quality(pc, ctx, fe, params)
+            del fe
 
     # old vertices whose polarity mask or absent set changed, per level
     # (a counting pass, untimed: the timed steps do not count)
@@ -252,8 +386,9 @@ def main():
         },
         "time_to_exact_ms": round(t_exact, 4),
         "level_done_ms": {str(k): round(float(v), 4) for k, v in zip(levels, med_lvl)},
-        "preview_f1_at_10pct": round(f1, 4),
-        "preview_level_at_10pct": kprev,
+        "preview_f1_at_10pct": (previews[WORKLOAD]["plain"]["f1"]["10%"]
+                                if previews else None),
+        "preview": previews or None,
         "direct_level0_gvps": round(sizes[0] / (direct_ms * 1e-3) / 1e9, 2),
         "direct_level0_ms": round(direct_ms, 4),
         "per_level": per_level,
@@ -275,13 +410,24 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        # the worker pool is sized to this process's share of the host
+        # (OMP_NUM_THREADS when set), at most the CPUs it may run on
+        share = int(os.environ.get("OMP_NUM_THREADS", avail) or avail)
+        threads = max(1, min(share, avail))
         planes = min(args.cpu_planes, shape[0])
+        planes1 = min(max(planes // 16, 2), shape[0])
         oracle.classify(f[:4], threads=threads)  # page in, build check
         t0 = time.perf_counter()
         res = oracle.classify(f, level=0, slow_range=(0, planes), threads=threads)
         cpu_s = time.perf_counter() - t0
+        assert res.status == 0
+        t0 = time.perf_counter()
+        res1 = oracle.classify(f, level=0, slow_range=(0, planes1), threads=1)
+        cpu1_s = time.perf_counter() - t0
+        assert res1.status == 0
         nv = planes * shape[1] * shape[2]
+        nv1 = planes1 * shape[1] * shape[2]
         out["cpu_baseline"] = {
             "value": round(nv / cpu_s / 1e9, 5),
             "unit": "Gvertices/s",
@@ -289,9 +435,13 @@ def main():
             "kind": "oracle",
             "sample": f"level-0 classification (codes + ascending list) of "
                       f"z-planes 0..{planes - 1} of the 512^3 field "
-                      f"({nv} vertices, {cpu_s:.2f} s)",
+                      f"({nv} vertices, {cpu_s:.2f} s on {threads} threads)",
+            "value_1thread": round(nv1 / cpu1_s / 1e9, 5),
+            "sample_1thread": f"z-planes 0..{planes1 - 1} ({nv1} vertices, {cpu1_s:.2f} s)",
+            "cpu_model": cpu_model(),
+            "cpus_visible": os.cpu_count(),
+            "cpus_allowed": avail,
         }
-        assert res.status == 0
     print(json.dumps(out))
 
 

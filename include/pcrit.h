@@ -181,11 +181,13 @@ typedef void (*pcrit_level_cb)(int level, int64_t count, void *user);
  *   crit_codes    device or NULL, as for pcrit_classify
  *   level_offsets_host  host, k_max+2 entries or NULL: the list of level k
  *                 is crit[off[i] .. off[i+1]) with i = k_max - k
- *   level_ms_host host, k_max+1 entries or NULL: milliseconds from the first
- *                 enqueued kernel to the completion of level k, at index
- *                 i = k_max - k (stream-event timing; NULL records no
- *                 events).  Levels whose work shares one launch (see below)
- *                 report the same time
+ *   level_ms_host host, k_max+1 entries or NULL: milliseconds from the start
+ *                 of the call's first kernel to the completion of level k,
+ *                 at index i = k_max - k (stream-event timing; NULL records
+ *                 no events).  The start event follows a 0.3 ms wait on the
+ *                 GPU by which the host has queued the call's kernels, so
+ *                 host launch latency stays out.  Levels whose work shares
+ *                 one launch (see below) report the same time
  *   reclassified_host  host, k_max+1 entries or NULL: number of old vertices
  *                 whose polarity mask or absent set changed at each level
  *                 (index i; 0 for level k_max).  Non-NULL makes the call
@@ -284,14 +286,18 @@ int pcrit_preview_f1_levels(int64_t nx, int64_t ny, int64_t nz,
  * / 8 with n_min the shortest axis, then 4 zeros: 32 BF16 values per vertex
  * (uint16 bit patterns).  The network is 32 -> 64 -> 64 -> 1: h1 = GELU(x W1
  * + b1), h2 = GELU(h1 W2 + b2), logit = h2 . w3 + b3, GELU(u) = u/2 (1 +
- * erf(u / sqrt 2)).  Parameters: PCRIT_MLP_PARAMS floats, FP32, in the
+ * erf(u / sqrt 2)) (the kernels evaluate erf to within 1.5e-7, Abramowitz
+ * and Stegun 7.1.26).  Parameters: PCRIT_MLP_PARAMS floats, FP32, in the
  * order W1 [32][64] (input-major), b1 [64], W2 [64][64], b2 [64], w3 [64],
  * b3.  The kernels round W1, W2 and w3 to BF16 (nearest even), x and h1 are
  * BF16, products accumulate in FP32; b1, b2, b3, h2 and the output are FP32.
- * Its training target for a vertex v of level k (stride s) is 1 iff a
- * full-resolution vertex within [v - s/2, v + s/2) on every axis is critical
- * (level-0 code).  A region's score is the sum of the sigmoid of its
- * vertices' logits; regions are refined by decreasing score.
+ * Its training target for a vertex v of level k (stride s) is the fraction
+ * of critical vertices (level-0 codes) among the full-resolution vertices
+ * within [v - s/2, v + s/2) on every axis (clipped to the grid), stored as
+ * the byte ceil(255 * count / volume) and read as byte / 255.  A region's
+ * score is the sum of the sigmoid of its vertices' logits (an estimate of
+ * its number of exact critical points over the cell volume); regions are
+ * refined by decreasing score.
  * ---------------------------------------------------------------------- */
 #define PCRIT_MLP_PARAMS 6337
 #define PCRIT_MLP_INPUTS 32
@@ -306,7 +312,8 @@ int pcrit_mlp_features(pcrit_ctx *ctx, void *hip_stream, const float *field,
                        int64_t nx, int64_t ny, int64_t nz, int level, uint16_t *X);
 
 /* Training targets of the vertices of level `level` from full-resolution
- * level-0 codes (device): labels[i] = 0 or 1 (device, n_level bytes). */
+ * level-0 codes (device): labels[i] = ceil(255 * critical fraction of the
+ * cell) (device, n_level bytes). */
 int pcrit_mlp_labels(pcrit_ctx *ctx, void *hip_stream, const uint8_t *codes,
                      int64_t nx, int64_t ny, int64_t nz, int level, uint8_t *labels);
 
@@ -315,7 +322,7 @@ int pcrit_mlp_forward(pcrit_ctx *ctx, void *hip_stream, const float *params,
                       const uint16_t *X, int64_t n, float *logits);
 
 /* Gradient of the mean binary cross-entropy of the logits of X against
- * labels (0/1) with respect to params: written to grad (PCRIT_MLP_PARAMS
+ * the targets labels / 255 with respect to params: written to grad (PCRIT_MLP_PARAMS
  * floats, overwritten); *loss (device float) receives the sum of the
  * per-sample losses.  The weight-gradient products run on the matrix cores
  * with BF16 operands (the back-propagated signals and the activations
@@ -342,7 +349,10 @@ int pcrit_region_count(int64_t nx, int64_t ny, int64_t nz, int region_edge,
  * two launches (levels of at most 2^18 vertices, then the others up to
  * 2^22), and each later level that takes the quad tiles is classified region
  * by region in the chosen order, the wave that finishes a region's last
- * tile recording the GPU clock.  The call synchronises at its end.
+ * tile recording the GPU clock.  Times count from a first stamp that the GPU
+ * takes after a 0.3 ms wait, by which time the host has queued the call's
+ * kernels (so host launch latency stays out of them).  The call synchronises
+ * at its end.
  *   order_mode        0: regions in id order; 1: rank_host[r] is the
  *                     position of region r (a permutation); 2: learned, from
  *                     the network with parameters mlp_params (device), run
@@ -351,9 +361,8 @@ int pcrit_region_count(int64_t nx, int64_t ny, int64_t nz, int region_edge,
  *                     then rank_host, if not NULL, receives the positions
  *                     used (the identity if no level is refined by regions)
  *   level_offsets_host  as for pcrit_progressive (k_max+2 entries)
- *   level_ms_host     k_max+1 doubles: milliseconds from the call's first
- *                     kernel until level k's list is complete (index
- *                     i = k_max - k)
+ *   level_ms_host     k_max+1 doubles: milliseconds from the first stamp
+ *                     until level k's list is complete (index i = k_max - k)
  *   region_ms_host    (k_max+1) x n_regions doubles: [i][r] = milliseconds
  *                     until level k of region r was classified (for levels
  *                     not refined by regions, the level's list time)

@@ -83,6 +83,8 @@ def forward(params, x, rounding=True):
 
 
 def loss_sum(params, x, y, rounding=True):
+    """Sum over samples of the binary cross-entropy of the logits against
+    targets y in [0, 1] (the library's target bytes / 255)."""
     z, _ = forward(params, x, rounding)
     y = np.asarray(y, dtype=np.float64)
     return float(np.sum(np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))))
@@ -136,8 +138,9 @@ def features(f, level):
 
 
 def labels(codes, level):
-    """Targets of the vertices of level `level`: 1 iff a full-resolution
-    vertex within [v - s/2, v + s/2) along every axis is critical."""
+    """Target bytes of the vertices of level `level`: ceil(255 * fraction of
+    critical full-resolution vertices within [v - s/2, v + s/2) along every
+    axis, clipped to the grid)."""
     codes = np.asarray(codes, dtype=np.uint8)
     nz, ny, nx = codes.shape
     s = 1 << level
@@ -151,7 +154,8 @@ def labels(codes, level):
             y0, y1 = max(y * s - h, 0), min(y * s + s - h, ny)
             for x in range(mx):
                 x0, x1 = max(x * s - h, 0), min(x * s + s - h, nx)
-                out[z, y, x] = crit[z0:z1, y0:y1, x0:x1].any()
+                cell = crit[z0:z1, y0:y1, x0:x1]
+                out[z, y, x] = -(-255 * int(cell.sum()) // cell.size)
     return out.ravel()
 
 

@@ -545,8 +545,8 @@ def mlp_features(field, level: int, *, ctx: Optional[Context] = None, out=None,
 
 def mlp_labels(codes, level: int, *, ctx: Optional[Context] = None, out=None,
                stream=None):
-    """Training targets (uint8 0/1) of the vertices of level ``level`` from
-    full-resolution level-0 codes."""
+    """Training targets (uint8, ceil(255 x critical fraction of the cell)) of
+    the vertices of level ``level`` from full-resolution level-0 codes."""
     import torch
     if codes.dtype != torch.uint8 or not codes.is_contiguous():
         raise PcritError(E_ARG, "codes must be contiguous uint8")

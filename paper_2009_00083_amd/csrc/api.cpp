@@ -113,7 +113,15 @@ struct pcrit_ctx {
   hipEvent_t last_kev = nullptr;
   void *tl = nullptr;  // region timeline and learned-order scratch
   int64_t tl_bytes = 0;
+  // second stream (default priority) on which the learned order is scored
+  // while the leading levels run, and the events that fork and join it
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
+
+// GPU wait ahead of the first stamp or start event of a timed call
+// (microseconds)
+constexpr double kTimelineLeadUs = 300.0;
 
 namespace {
 
@@ -200,6 +208,7 @@ struct RegionHooks {
   int *tile_list = nullptr, *scratch = nullptr;
   unsigned *left = nullptr;
   uint64_t *stamp = nullptr;  // this level's row of region stamps
+  bool prebuilt = false;      // tile lists already built (else built here)
 };
 
 int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
@@ -294,7 +303,8 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     if (rh) {
       const int s = (int)s0.g.s;
       plan_level_quad(q.lv, std::min(kQuadZChunk, rh->E / s));
-      if (launch_region_tiles(q.lv, kQuadRows, s, rh->E, rh->nry, rh->nregions, rh->rank,
+      if (!rh->prebuilt &&
+          launch_region_tiles(q.lv, kQuadRows, s, rh->E, rh->nry, rh->nregions, rh->rank,
                               rh->tile_list, rh->left, rh->scratch, st) != hipSuccess)
         return PCRIT_E_HIP;
       q.tile_list = rh->tile_list;
@@ -457,6 +467,9 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->reclass_acc);
   hipFree(c->tl);
   hipFree(c->status);
+  if (c->side) hipStreamDestroy(c->side);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   if (c->h_status) hipHostFree(c->h_status);
   if (c->ev_start) hipEventDestroy(c->ev_start);
   for (int i = 0; i <= kMaxLevels; i++)
@@ -645,7 +658,11 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
   // Completion events only when asked for: every record is a release on the
   // stream, which costs microseconds of GPU time.  Levels of one launch
   // complete together and share the event of its last level.
-  if (timed && hipEventRecord(c->ev_start, s) != hipSuccess) return PCRIT_E_HIP;
+  // The start event follows a short GPU wait by which the host has queued
+  // the call's kernels, so launch latency stays out of the level times.
+  if (timed && (launch_wait_stamp(nullptr, kTimelineLeadUs, s) != hipSuccess ||
+                hipEventRecord(c->ev_start, s) != hipSuccess))
+    return PCRIT_E_HIP;
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
     // the compaction of a last launch of one level publishes the offsets
@@ -764,7 +781,7 @@ int feature_level(int64_t nx, int64_t ny, int64_t nz, int kmax) {
   int best = 1;
   double err = 1e30;
   for (int k = 1; k <= kmax; k++) {
-    const double e = fabs(log2((double)nmin / (double)((int64_t)1 << k)) - 6.0);
+    const double e = fabs(log2((double)nmin / (double)((int64_t)1 << k)) - 5.0);
     if (e < err) {
       err = e;
       best = k;
@@ -917,8 +934,15 @@ int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *fiel
       set_quad(&steps[i].g, quad_eligible(field, nx, steps[i].g.s, steps[i].g.dim));
     i = j;
   }
-  // scratch: compaction as usual, then the timeline's own
-  int64_t need_words = 0, need_chunks = 0, max_tiles = 1;
+  // Levels refined by regions and their tile plans (as the launch makes
+  // them); their tile lists are built up front, on the side stream.
+  struct RegionalLevel {
+    int i;
+    LevelDesc l;
+    int64_t list_off;
+  };
+  std::vector<RegionalLevel> rl;
+  int64_t need_words = 0, need_chunks = 0, all_tiles = 0;
   for (int i = 0; i <= kmax; i = group_end[i]) {
     int64_t w, ch, lb;
     launch_needs(&steps[i], group_end[i] - i, false, &w, &ch, &lb);
@@ -930,30 +954,34 @@ int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *fiel
       l.my = (int)steps[i].g.my;
       l.mz = (int)steps[i].g.mz;
       plan_level_quad(l, std::min(kQuadZChunk, E / (int)steps[i].g.s));
-      max_tiles = std::max<int64_t>(max_tiles, l.ntiles);
+      rl.push_back({i, l, all_tiles});
+      all_tiles += l.ntiles;
     }
   }
+  const int nrl = (int)rl.size();
   st = ensure((void **)&c->bits, &c->bits_words, need_words * 8);
   if (!st) st = ensure((void **)&c->counts, &c->counts_n, need_chunks * (int64_t)sizeof(int));
   if (st) return st;
   const int lf = feature_level(nx, ny, nz, kmax);
-  const int64_t nq = level_vertices(geo[lf]);
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t left_bytes = up(4 * (int64_t)kCounterStride * nregions),
+                scr_bytes = up(4 * kRegionScratchInts(nregions));
   const int64_t o_stamp = 0, o_rstamp = o_stamp + up(8 * (kMaxLevels + 2)),
                 o_left = o_rstamp + up(8 * (int64_t)(kmax + 1) * nregions),
-                o_rank = o_left + up(4 * (int64_t)nregions),
+                o_rank = o_left + left_bytes * std::max(nrl, 1),
                 o_scr = o_rank + up(4 * (int64_t)nregions),
-                o_score = o_scr + up(4 * kRegionScratchInts(nregions)),
-                o_list = o_score + up(4 * (int64_t)nregions),
-                o_x = o_list + up(4 * max_tiles),
-                o_logit = o_x + (order_mode == 2 ? up(2 * kMlpIn * nq) : 0),
-                total = o_logit + (order_mode == 2 ? up(4 * nq) : 0);
+                o_score = o_scr + scr_bytes * std::max(nrl, 1),
+                o_list = o_score + up(4 * (int64_t)kCounterStride * nregions),
+                total = o_list + up(4 * std::max<int64_t>(all_tiles, 1));
   st = ensure(&c->tl, &c->tl_bytes, total);
   if (st) return st;
   char *tb = static_cast<char *>(c->tl);
   uint64_t *stamps = reinterpret_cast<uint64_t *>(tb + o_stamp);
   uint64_t *rstamps = reinterpret_cast<uint64_t *>(tb + o_rstamp);
   int *rank = reinterpret_cast<int *>(tb + o_rank);
+  auto level_left = [&](int k) { return reinterpret_cast<unsigned *>(tb + o_left + k * left_bytes); };
+  auto level_scr = [&](int k) { return reinterpret_cast<int *>(tb + o_scr + k * scr_bytes); };
+  auto level_list = [&](int k) { return reinterpret_cast<int *>(tb + o_list) + rl[k].list_off; };
   if (order_mode != 2) {
     std::vector<int> h(nregions);
     for (int r = 0; r < nregions; r++) h[r] = order_mode == 1 ? rank_host[r] : r;
@@ -965,41 +993,68 @@ int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *fiel
   if (hipMemsetAsync(rstamps, 0, 8 * (size_t)(kmax + 1) * nregions, s) != hipSuccess)
     return PCRIT_E_HIP;
 
+  const bool learn = order_mode == 2 && nrl > 0;
+  if (nrl > 0 && !c->side) {
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+      return PCRIT_E_HIP;
+  }
+
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
   int nstamp = 0;
   int stamp_of_group[kMaxLevels];
-  if (launch_stamp(&stamps[nstamp++], s) != hipSuccess) return PCRIT_E_HIP;
-  bool ordered = order_mode != 2;
+  // the clock starts once the host has queued the call's work: a short
+  // wait on the GPU ahead of the first stamp keeps launch latency out of
+  // the timeline
+  if (launch_wait_stamp(&stamps[nstamp++], kTimelineLeadUs, s) != hipSuccess)
+    return PCRIT_E_HIP;
+  if (nrl > 0) {
+    // on the side stream, overlapping the leading levels: the learned order
+    // (inputs of level lf, logits, region scores, ranks), then the tile
+    // lists of every region-refined level
+    hipStream_t s2 = c->side;
+    if (hipEventRecord(c->ev_fork, s) != hipSuccess ||
+        hipStreamWaitEvent(s2, c->ev_fork, 0) != hipSuccess)
+      return PCRIT_E_HIP;
+    if (learn) {
+      float *score = reinterpret_cast<float *>(tb + o_score);
+      const Geom &gf = geo[lf];
+      if (launch_mlp_region_scores(mlp_params, field, nx, ny, (int)gf.s, (int)gf.mx, (int)gf.my,
+                                   (int)gf.mz, resolution_feature(nx, ny, nz, lf), E, nry,
+                                   nregions, score, s2) != hipSuccess ||
+          launch_region_rank(score, kCounterStride, nregions, rank, s2) != hipSuccess)
+        return PCRIT_E_HIP;
+    }
+    for (int k = 0; k < nrl; k++)
+      if (launch_region_tiles(rl[k].l, kQuadRows, (int)steps[rl[k].i].g.s, E, nry, nregions, rank,
+                              level_list(k), level_left(k), level_scr(k), s2) != hipSuccess)
+        return PCRIT_E_HIP;
+    if (hipEventRecord(c->ev_join, s2) != hipSuccess) return PCRIT_E_HIP;
+  }
+  bool joined = false;
+  int k_rl = 0;
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
     const bool regional = n == 1 && steps[i].g.quad;
     RegionHooks rh;
     if (regional) {
-      if (!ordered) {
-        // learned order: features of level lf, logits, region scores, ranks
-        uint16_t *X = reinterpret_cast<uint16_t *>(tb + o_x);
-        float *logit = reinterpret_cast<float *>(tb + o_logit);
-        float *score = reinterpret_cast<float *>(tb + o_score);
-        const Geom &gf = geo[lf];
-        if (launch_mlp_features(field, nx, ny, nz, (int)gf.s, (int)gf.mx, (int)gf.my,
-                                (int)gf.mz, resolution_feature(nx, ny, nz, lf), X,
-                                s) != hipSuccess ||
-            launch_mlp_forward(mlp_params, X, nq, logit, s) != hipSuccess ||
-            launch_region_scores(logit, (int)gf.s, (int)gf.mx, (int)gf.my, (int)gf.mz, E, nry,
-                                 nregions, score, s) != hipSuccess ||
-            launch_region_rank(score, nregions, rank, s) != hipSuccess)
-          return PCRIT_E_HIP;
-        ordered = true;
+      if (!joined) {
+        // the first region-refined level waits for the side stream
+        if (hipStreamWaitEvent(s, c->ev_join, 0) != hipSuccess) return PCRIT_E_HIP;
+        joined = true;
       }
       rh.E = E;
       rh.nry = nry;
       rh.nregions = nregions;
       rh.rank = rank;
-      rh.tile_list = reinterpret_cast<int *>(tb + o_list);
-      rh.scratch = reinterpret_cast<int *>(tb + o_scr);
-      rh.left = reinterpret_cast<unsigned *>(tb + o_left);
+      rh.tile_list = level_list(k_rl);
+      rh.scratch = level_scr(k_rl);
+      rh.left = level_left(k_rl);
       rh.stamp = rstamps + (int64_t)i * nregions;
+      rh.prebuilt = true;
+      k_rl++;
     }
     st = enqueue_group(c, s, field, &steps[i], n, codes, crit, nullptr, crit_capacity, nullptr,
                        gen, i + n > kmax, c->bits, c->counts, nullptr, 0,
@@ -1010,7 +1065,7 @@ int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *fiel
   }
   std::vector<uint64_t> hs(nstamp), hr((size_t)(kmax + 1) * nregions);
   if (order_mode == 2 && rank_host) {
-    if (!ordered) {
+    if (!learn) {
       for (int r = 0; r < nregions; r++) rank_host[r] = r;
     } else if (hipMemcpyAsync(rank_host, rank, sizeof(int) * nregions, hipMemcpyDeviceToHost,
                               s) != hipSuccess) {

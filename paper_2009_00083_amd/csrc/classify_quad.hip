@@ -443,6 +443,10 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
   }
 }
 
+// s_waitcnt operand: vmcnt 0, expcnt and lgkmcnt unconstrained (GFX9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVmem = 0x0F70;
+
 // LISTED: tiles from the region-ordered per-XCD lists (QuadArgs::tile_list)
 // instead of a grid-stride walk over the level.
 template <int R, int SX, bool LISTED>
@@ -470,7 +474,7 @@ void classify3d_quad_kernel(QuadArgs a) {
     int t;
     if (LISTED) {
       int i = 0;
-      if (lane == 0) i = atomicAdd(&a.queue[x], 1);
+      if (lane == 0) i = atomicAdd(&a.queue[kCounterStride * x], 1);
       i = __builtin_amdgcn_readfirstlane(i);
       if (i >= nlist) break;
       t = a.tile_list[beg + i];
@@ -489,12 +493,13 @@ void classify3d_quad_kernel(QuadArgs a) {
       quad_tile<R, SX, true>(a, t, lane, slut, nan_seen);
     if (LISTED) {
       // the region's last tile stamps the clock once this tile's stores
-      // are complete
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // have completed (a wait on the vector memory counter only: a
+      // release fence at device scope would also write back the XCD's L2)
+      __builtin_amdgcn_s_waitcnt(kWaitVmem);
       if (lane == 0) {
         const int r = ((p.zc * a.lv.zchunk * SX) / a.region_edge) * a.nry +
                       (p.ty * R * SX) / a.region_edge;
-        if (atomicSub(&a.region_left[r], 1u) == 1u)
+        if (atomicSub(&a.region_left[kCounterStride * r], 1u) == 1u)
           a.region_stamp[r] = __builtin_amdgcn_s_memrealtime();
       }
     }
@@ -514,12 +519,17 @@ constexpr int64_t kQuadWantTiles = 4096;
 
 }  // namespace
 
-void plan_level_quad(LevelDesc &l, int zchunk) {
+void plan_level_quad(LevelDesc &l, int zmax) {
   l.ntx = (l.mx + kQuadCols - 1) / kQuadCols;
   l.nty = (l.my + kQuadRows - 1) / kQuadRows;
   int d = kQuadZChunk;
   while (d > 2 && (int64_t)l.ntx * l.nty * ((l.mz + d - 1) / d) < kQuadWantTiles) d -= 2;
-  l.zchunk = zchunk > 0 ? zchunk : d;
+  if (zmax > 0) {
+    int p = 2;
+    while (2 * p <= std::min(d, zmax)) p *= 2;
+    d = p;
+  }
+  l.zchunk = d;
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor((uint32_t)l.nty, &l.nty_mul, &l.nty_shift);

@@ -1,7 +1,7 @@
 // Learned refinement order (gfx950): a small MLP scores the coarse vertices
-// of a level by how likely their cell holds a critical point of the exact
-// (full-resolution) classification; regions are refined in the order of
-// their summed scores.  The classification itself never depends on it: every
+// of a level by the density of critical points of the exact (full-resolution)
+// classification in their cells; regions are refined in the order of their
+// summed scores.  The classification itself never depends on it: every
 // vertex of every level is still classified by the classification kernels,
 // so the final result is the same whatever the order.
 //
@@ -47,13 +47,31 @@ __device__ __forceinline__ int unit_of_pos(int p) {
   return 16 * (2 * kk + (t >> 2)) + 4 * g + (t & 3);
 }
 
+// Standard normal CDF Phi(u) = (1 + erf(u / sqrt 2)) / 2, with erf from
+// Abramowitz and Stegun 7.1.26 (|error| <= 1.5e-7 on erf): for x >= 0,
+// 1 - erf(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p x).  Branch free: the tail q = 1 - erf(|u| / sqrt 2) gives
+// Phi = q / 2 for u < 0 and 1 - q / 2 otherwise, without cancellation in
+// the lower tail.  *e receives exp(-u^2 / 2), which the derivative reuses.
+__device__ __forceinline__ float normal_cdf(float u, float *e) {
+  const float x = fabsf(u) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  float poly = fmaf(t, 1.061405429f, -1.453152027f);
+  poly = fmaf(t, poly, 1.421413741f);
+  poly = fmaf(t, poly, -0.284496736f);
+  poly = fmaf(t, poly, 0.254829592f);
+  *e = __builtin_amdgcn_exp2f(-x * x * 1.4426950408889634f);
+  const float hq = 0.5f * t * poly * *e;
+  return u < 0.f ? hq : 1.0f - hq;
+}
 __device__ __forceinline__ float gelu(float x) {
-  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+  float e;
+  return x * normal_cdf(x, &e);
 }
 __device__ __forceinline__ float gelu_grad(float x) {
-  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
-  const float pdf = 0.39894228040143268f * __expf(-0.5f * x * x);
-  return cdf + x * pdf;
+  float e;
+  const float cdf = normal_cdf(x, &e);
+  return cdf + x * 0.39894228040143268f * e;
 }
 
 // Weight fragments of one wave (A operands) and the per-lane biases.
@@ -161,7 +179,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *params,
 }
 
 // Gradient of the mean binary cross-entropy (with logits) of n samples
-// against labels y (0/1 bytes), added to grad (kMlpParams floats, FP32,
+// against the targets y / 255 (bytes), added to grad (kMlpParams floats, FP32,
 // zeroed by the caller); the loss sum is added to loss_acc[0].  One wave
 // handles 32 samples at a time (two groups of 16): the K dimension of the
 // weight-gradient products is the sample.  LDS holds the wave's activations
@@ -221,7 +239,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(const float *params,
       MlpActs A;
       const float z = column_sum(forward16(W, xb, A)) + W.b3;
       // d loss / d z for this sample (0 for padding samples)
-      const float yv = ok ? (float)y[s] : 0.f;
+      const float yv = ok ? (float)y[s] * (1.0f / 255.0f) : 0.f;
       const float sig = 1.0f / (1.0f + __expf(-z));
       const float dz = ok ? (sig - yv) * inv_n : 0.f;
       if (g == 0 && ok) {
@@ -389,9 +407,11 @@ __global__ void mlp_features_kernel(const float *f, int64_t nx, int64_t ny, int6
   for (int k = 0; k < 4; k++) dst[k] = __builtin_bit_cast(uint4, *reinterpret_cast<bf16x8 *>(&out[8 * k]));
 }
 
-// Label of coarse vertex q of level `level` (stride s): 1 iff a vertex of
-// the full-resolution grid within [v - s/2, v + s/2) on every axis (its cell)
-// is critical in `codes` (full-resolution codes of level 0).
+// Target of coarse vertex q of level `level` (stride s): the fraction of
+// critical vertices (full-resolution codes of level 0) among the vertices of
+// the full-resolution grid within [v - s/2, v + s/2) on every axis (its
+// cell, clipped to the grid), as ceil(255 * count / volume): 0 only for no
+// critical vertex, 255 only when all are.
 __global__ void mlp_labels_kernel(const uint8_t *codes, int64_t nx, int64_t ny, int64_t nz,
                                   int s, int mx, int my, int mz, uint8_t *label) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -402,34 +422,109 @@ __global__ void mlp_labels_kernel(const uint8_t *codes, int64_t nx, int64_t ny, 
   const int x0 = max(x * s - h, 0), x1 = min(x * s + s - h, (int)nx);
   const int y0 = max(y * s - h, 0), y1 = min(y * s + s - h, (int)ny);
   const int z0 = max(z * s - h, 0), z1 = min(z * s + s - h, (int)nz);
-  unsigned any = 0;
-  for (int zz = z0; zz < z1 && !any; zz++)
-    for (int yy = y0; yy < y1 && !any; yy++) {
+  unsigned cnt = 0;
+  for (int zz = z0; zz < z1; zz++)
+    for (int yy = y0; yy < y1; yy++) {
       const uint8_t *row = codes + ((int64_t)zz * ny + yy) * nx;
-      for (int xx = x0; xx < x1; xx++) any |= (row[xx] & 0xBFu) != 0x09u;
+      for (int xx = x0; xx < x1; xx++) cnt += (row[xx] & 0xBFu) != 0x09u;
     }
-  label[q] = (uint8_t)any;
+  const uint64_t vol = (uint64_t)(x1 - x0) * (y1 - y0) * (z1 - z0);
+  label[q] = (uint8_t)((255u * (uint64_t)cnt + vol - 1) / vol);
 }
 
-// Region scores: region (ry, rz) of edge E (full resolution, along y and z)
-// sums the sigmoid of the logits of the coarse vertices (level stride s)
-// whose y and z lie in it.
-__global__ void region_scores_kernel(const float *logits, int s, int mx, int my, int mz, int E,
-                                     int nry, float *scores) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nq = (int64_t)mx * my * mz;
-  if (q >= nq) return;
-  const int y = (int)((q / mx) % my), z = (int)(q / ((int64_t)mx * my));
-  const int r = ((z * s) / E) * nry + (y * s) / E;
-  atomicAdd(&scores[r], 1.f / (1.f + __expf(-logits[q])));
+// Region scores straight from the field: the inputs of each coarse vertex
+// (as mlp_features_kernel, the four lanes of a sample computing eight of
+// them each), the network (forward16), the sigmoid, summed per region.
+// Every wave takes a contiguous run of 16-sample groups, so a lane's
+// samples stay in one region for many groups; each lane flushes its running
+// sum with one atomic add when its region changes (scores spaced
+// kCounterStride floats apart, zeroed by the caller).
+__global__ __launch_bounds__(256) void mlp_region_scores_kernel(
+    const float *params, const float *f, int64_t nx, int64_t ny, int s, int mx, int my, int mz,
+    float res, int E, int nry, float *scores) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  MlpWeights W;
+  load_weights(params, lane, W);
+  const int64_t n = (int64_t)mx * my * mz, groups = (n + 15) / 16;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t wv = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t g0 = groups * wv / nw, g1 = groups * (wv + 1) / nw;
+  float acc = 0.f;
+  int cur = -1;
+  // this lane's samples of group grp: centre and its eight neighbour
+  // differences, loaded one group ahead of the network
+  struct Sample {
+    float c, v[8];
+    int r;
+    bool ok;
+  };
+  // level vertex counts fit in 32 bits (the grid has at most 2^32
+  // vertices and the level at least stride 2), so the index arithmetic is
+  // 32-bit; addresses step by the level's strides
+  const int64_t sy = (int64_t)s * nx, sz = (int64_t)s * nx * ny;
+  auto fetch = [&](int64_t grp, Sample &S) {
+    const int64_t q = grp * 16 + j;
+    S.ok = q < n;
+    const uint32_t qq = (uint32_t)(S.ok ? q : n - 1);
+    const uint32_t row = qq / (uint32_t)mx;
+    const int x = (int)(qq - row * (uint32_t)mx);
+    const int z = (int)(row / (uint32_t)my), y = (int)(row - (uint32_t)z * (uint32_t)my);
+    S.r = ((z * s) / E) * nry + (y * s) / E;
+    const float *cp = f + z * sz + y * sy + (int64_t)x * s;
+    S.c = *cp;
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      const int k = 8 * g + t;
+      S.v[t] = S.c;
+      if (k < 27) {
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+        const int ex = min(max(x + dx, 0), mx - 1) - x, ey = min(max(y + dy, 0), my - 1) - y,
+                  ez = min(max(z + dz, 0), mz - 1) - z;
+        S.v[t] = cp[ez * sz + ey * sy + ex * s];
+      }
+    }
+  };
+  Sample S;
+  if (g0 < g1) fetch(g0, S);
+  for (int64_t grp = g0; grp < g1; grp++) {
+    const Sample C = S;
+    if (grp + 1 < g1) fetch(grp + 1, S);
+    float v[8];
+    float mag = 0.f;
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      v[t] = C.v[t] - C.c;
+      mag = fmaxf(mag, fabsf(v[t]));
+    }
+    mag = fmaxf(mag, __shfl_xor(mag, 16));
+    mag = fmaxf(mag, __shfl_xor(mag, 32));
+    const float inv = mag > 0.f ? 1.f / mag : 0.f;
+    bf16x8 xb;
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      const int k = 8 * g + t;
+      xb[t] = (__bf16)(k < 27 ? v[t] * inv : (k == 27 ? res : 0.f));
+    }
+    MlpActs A;
+    const float zl = column_sum(forward16(W, xb, A)) + W.b3;
+    if (g == 0 && C.ok) {
+      if (C.r != cur) {
+        if (cur >= 0) atomicAdd(&scores[kCounterStride * cur], acc);
+        cur = C.r;
+        acc = 0.f;
+      }
+      acc += 1.f / (1.f + __expf(-zl));
+    }
+  }
+  if (g == 0 && cur >= 0) atomicAdd(&scores[kCounterStride * cur], acc);
 }
 
 // Rank of each region: number of regions with a higher score, or an equal
 // score and a smaller id (one block, nregions <= kMaxRegions).
-__global__ __launch_bounds__(1024) void region_rank_kernel(const float *scores, int nregions,
-                                                           int *rank) {
+__global__ __launch_bounds__(1024) void region_rank_kernel(const float *scores, int stride,
+                                                           int nregions, int *rank) {
   __shared__ float s_sc[kMaxRegions];
-  for (int i = threadIdx.x; i < nregions; i += blockDim.x) s_sc[i] = scores[i];
+  for (int i = threadIdx.x; i < nregions; i += blockDim.x) s_sc[i] = scores[(int64_t)stride * i];
   __syncthreads();
   for (int r = threadIdx.x; r < nregions; r += blockDim.x) {
     const float v = s_sc[r];
@@ -451,21 +546,21 @@ __device__ __forceinline__ RegionTiles region_tiles(const LevelDesc &l, int R, i
           min((rz + 1) * ez, nzc)};
 }
 
-// Region tile counts, and where part x of each region starts in tile list
-// x (regions in rank order), one block: offset[kXcds r + x]; then the start
-// of every list (xcd_off, kXcds + 1 entries) and zero queue counters.
-__global__ __launch_bounds__(1024) void region_offsets_kernel(LevelDesc l, int R, int s, int E,
-                                                              int nry, int nregions,
-                                                              const int *rank,
-                                                              unsigned *region_left,
-                                                              int *scratch) {
-  __shared__ int s_cnt[kMaxRegions];               // tile count of the region at each rank
-  __shared__ int s_pre[kXcds][kMaxRegions + 1];    // part-x tiles of the ranks before
-  __shared__ int s_off[kXcds + 1];
+// Tile lists of a level in region order, first step (one block): region
+// tile counts, where part x of the region at each rank starts in list x
+// (regions in rank order; region_part_start), the start of every list
+// (xcd_off, kXcds + 1 entries) and zero queue counters.
+__global__ __launch_bounds__(1024) void region_parts_kernel(LevelDesc l, int R, int s, int E,
+                                                            int nry, int nregions,
+                                                            const int *rank,
+                                                            unsigned *region_left,
+                                                            int *scratch) {
+  __shared__ int s_cnt[kMaxRegions];                // tile count of the region at each rank
+  __shared__ int s_pre[kXcds][kMaxRegions + 1];     // part-x tiles of the ranks before
   for (int r = threadIdx.x; r < nregions; r += blockDim.x) {
     const RegionTiles t = region_tiles(l, R, s, E, r % nry, r / nry);
     const int c = l.ntx * max(t.ty1 - t.ty0, 0) * max(t.zc1 - t.zc0, 0);
-    region_left[r] = (unsigned)c;
+    region_left[kCounterStride * r] = (unsigned)c;
     s_cnt[rank[r]] = c;
   }
   __syncthreads();
@@ -480,31 +575,32 @@ __global__ __launch_bounds__(1024) void region_offsets_kernel(LevelDesc l, int R
     s_pre[x][nregions] = acc;
   }
   __syncthreads();
-  int *xcd_off = region_xcd_off(scratch, nregions);
+  __shared__ int s_off[kXcds];
   if (threadIdx.x == 0) {
+    int *xcd_off = region_xcd_off(scratch, nregions);
     int acc = 0;
     for (int x = 0; x < kXcds; x++) {
       s_off[x] = acc;
       xcd_off[x] = acc;
       acc += s_pre[x][nregions];
     }
-    s_off[kXcds] = acc;
     xcd_off[kXcds] = acc;
     int *queue = region_queue(scratch, nregions);
-    for (int x = 0; x < kXcds; x++) queue[x] = 0;
+    for (int x = 0; x < kXcds; x++) queue[kCounterStride * x] = 0;
   }
   __syncthreads();
+  int *start = region_part_start(scratch, nregions);
   for (int i = threadIdx.x; i < kXcds * nregions; i += blockDim.x) {
-    const int r = i / kXcds, x = i % kXcds;
-    scratch[i] = s_off[x] + s_pre[x][rank[r]];
+    const int k = i / kXcds, x = i % kXcds;
+    start[i] = s_off[x] + s_pre[x][k];
   }
 }
 
-// Places every tile of the level: tile i of its region (x fastest, then
-// rows, then chunks) falls in part x = the one of the kXcds contiguous parts
+// Second step: every tile placed; tile i of its region (x fastest, then
+// rows, then chunks) falls in part x, the one of the kXcds contiguous parts
 // that holds i.
-__global__ void region_tile_list_kernel(LevelDesc l, int R, int s, int E, int nry,
-                                        const int *offset, int *tile_list) {
+__global__ void region_place_kernel(LevelDesc l, int R, int s, int E, int nry, int nregions,
+                                    const int *rank, const int *scratch, int *tile_list) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= l.ntiles) return;
   const TilePos p = tile_pos(l, t);
@@ -514,18 +610,34 @@ __global__ void region_tile_list_kernel(LevelDesc l, int R, int s, int E, int nr
   const int64_t c = (int64_t)l.ntx * (rt.ty1 - rt.ty0) * (rt.zc1 - rt.zc0);
   int x = kXcds - 1;
   while (x > 0 && c * x / kXcds > local) x--;
-  tile_list[offset[(rz * nry + ry) * kXcds + x] + local - (int)(c * x / kXcds)] = t;
+  const int *start = region_part_start(const_cast<int *>(scratch), nregions);
+  tile_list[start[kXcds * rank[rz * nry + ry] + x] + local - (int)(c * x / kXcds)] = t;
 }
 
 __global__ void stamp_kernel(uint64_t *out) {
   if (threadIdx.x == 0) *out = __builtin_amdgcn_s_memrealtime();
 }
 
+// Waits `ticks` of the 100 MHz clock (at most 2^20 short sleeps), then
+// stores the clock in *out (if out is not null).
+__global__ void wait_stamp_kernel(uint64_t *out, uint64_t ticks) {
+  if (threadIdx.x == 0) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int i = 0; i < (1 << 20); i++) {
+      if (__builtin_amdgcn_s_memrealtime() - t0 >= ticks) break;
+      __builtin_amdgcn_s_sleep(8);
+    }
+    if (out) *out = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
 }  // namespace
 
-hipError_t launch_region_rank(const float *scores, int nregions, int *rank, hipStream_t st) {
+hipError_t launch_region_rank(const float *scores, int stride, int nregions, int *rank,
+                              hipStream_t st) {
   if (nregions < 1 || nregions > kMaxRegions) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(region_rank_kernel, dim3(1), dim3(1024), 0, st, scores, nregions, rank);
+  hipLaunchKernelGGL(region_rank_kernel, dim3(1), dim3(1024), 0, st, scores, stride, nregions,
+                     rank);
   return hipGetLastError();
 }
 
@@ -533,10 +645,15 @@ hipError_t launch_region_tiles(const LevelDesc &l, int R, int s, int E, int nry,
                                const int *rank, int *tile_list, unsigned *region_left,
                                int *scratch, hipStream_t st) {
   if (nregions < 1 || nregions > kMaxRegions) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(region_offsets_kernel, dim3(1), dim3(1024), 0, st, l, R, s, E, nry,
-                     nregions, rank, region_left, scratch);
-  hipLaunchKernelGGL(region_tile_list_kernel, dim3((l.ntiles + 255) / 256), dim3(256), 0, st, l,
-                     R, s, E, nry, scratch, tile_list);
+  hipLaunchKernelGGL(region_parts_kernel, dim3(1), dim3(1024), 0, st, l, R, s, E, nry, nregions,
+                     rank, region_left, scratch);
+  hipLaunchKernelGGL(region_place_kernel, dim3((l.ntiles + 255) / 256), dim3(256), 0, st, l, R, s,
+                     E, nry, nregions, rank, scratch, tile_list);
+  return hipGetLastError();
+}
+
+hipError_t launch_wait_stamp(uint64_t *out, double us, hipStream_t st) {
+  hipLaunchKernelGGL(wait_stamp_kernel, dim3(1), dim3(64), 0, st, out, (uint64_t)(us * 100.0));
   return hipGetLastError();
 }
 
@@ -548,7 +665,8 @@ hipError_t launch_stamp(uint64_t *out, hipStream_t st) {
 hipError_t launch_mlp_forward(const float *params, const uint16_t *X, int64_t n, float *logits,
                               hipStream_t st) {
   const int64_t groups = (n + 15) / 16;
-  const int blocks = (int)std::min<int64_t>((groups + 3) / 4, 4096);
+  // each wave loads the weights once and then takes groups of 16 samples
+  const int blocks = (int)std::min<int64_t>((groups + 3) / 4, 1024);
   hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, params, X,
                      n, logits);
   return hipGetLastError();
@@ -589,14 +707,17 @@ hipError_t launch_mlp_labels(const uint8_t *codes, int64_t nx, int64_t ny, int64
   return hipGetLastError();
 }
 
-hipError_t launch_region_scores(const float *logits, int s, int mx, int my, int mz, int E,
-                                int nry, int nregions, float *scores, hipStream_t st) {
-  const int64_t nq = (int64_t)mx * my * mz;
-  hipLaunchKernelGGL(fill_kernel, dim3((nregions + 255) / 256), dim3(256), 0, st, scores,
-                     nregions, 0.f);
-  hipLaunchKernelGGL(region_scores_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st,
-                     logits, s, mx, my, mz, E, nry, scores);
+hipError_t launch_mlp_region_scores(const float *params, const float *f, int64_t nx, int64_t ny,
+                                    int s, int mx, int my, int mz, float res, int E, int nry,
+                                    int nregions, float *scores, hipStream_t st) {
+  const int n = kCounterStride * nregions;
+  hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, scores, n, 0.f);
+  // two waves per SIMD (the weights live in registers); each wave loads
+  // them once and then takes a run of sample groups
+  hipLaunchKernelGGL(mlp_region_scores_kernel, dim3(512), dim3(256), 0, st, params, f, nx, ny, s,
+                     mx, my, mz, res, E, nry, scores);
   return hipGetLastError();
 }
+
 
 }  // namespace pcrit

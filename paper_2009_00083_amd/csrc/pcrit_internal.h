@@ -235,10 +235,10 @@ struct QuadArgs {
   unsigned gen;
   // Region timeline (null unless requested): the waves of XCD x take the
   // tiles of tile_list[xcd_off[x] ..] in order, one at a time, through the
-  // counter queue[x] (zero at launch); a tile belongs to region (rz, ry) of
-  // edge region_edge (full-resolution rows and planes); the wave that
-  // finishes a region's last tile (region_left counts down) stores the GPU
-  // clock in region_stamp.
+  // counter queue[kCounterStride x] (zero at launch); a tile belongs to
+  // region (rz, ry) of edge region_edge (full-resolution rows and planes);
+  // the wave that finishes a region's last tile (region_left[kCounterStride
+  // r] counts down) stores the GPU clock in region_stamp[r].
   const int *tile_list;
   const int *xcd_off;
   int *queue;
@@ -248,7 +248,8 @@ struct QuadArgs {
 };
 // Level geometry of a quad launch; whether a level can take one (stride 1
 // or 2, 16-byte aligned rows).
-void plan_level_quad(LevelDesc &l, int zchunk = 0);  // zchunk 0: chosen by size
+// zmax > 0: the depth is also a power of two that is at most zmax.
+void plan_level_quad(LevelDesc &l, int zmax = 0);
 bool quad_eligible(const float *field, int64_t nx, int64_t s, int dim);
 hipError_t launch_classify_quad(const QuadArgs &a, hipStream_t st);
 
@@ -279,25 +280,43 @@ hipError_t launch_mlp_features(const float *f, int64_t nx, int64_t ny, int64_t n
                                int mx, int my, int mz, float res, uint16_t *X, hipStream_t st);
 hipError_t launch_mlp_labels(const uint8_t *codes, int64_t nx, int64_t ny, int64_t nz, int s,
                              int mx, int my, int mz, uint8_t *label, hipStream_t st);
-hipError_t launch_region_scores(const float *logits, int s, int mx, int my, int mz, int E,
-                                int nry, int nregions, float *scores, hipStream_t st);
-// Region ranks from scores (descending score, then ascending region id).
-hipError_t launch_region_rank(const float *scores, int nregions, int *rank, hipStream_t st);
+// Region ranks from scores[stride r] (descending score, then ascending
+// region id).
+hipError_t launch_region_rank(const float *scores, int stride, int nregions, int *rank,
+                              hipStream_t st);
+// Region scores of the learned order straight from the field (inputs of
+// level stride s, network, sigmoid, per-region sums): scores[kCounterStride
+// r], kCounterStride * nregions floats, overwritten.
+hipError_t launch_mlp_region_scores(const float *params, const float *f, int64_t nx, int64_t ny,
+                                    int s, int mx, int my, int mz, float res, int E, int nry,
+                                    int nregions, float *scores, hipStream_t st);
 // Tile lists of a quad level for its region-ordered launch, and each
-// region's tile count in region_left.  The tiles of every region are split
+// region's tile count in region_left[kCounterStride r].  The tiles of every region are split
 // into kXcds contiguous parts; list x (at xcd_off[x] .. xcd_off[x + 1] of
 // tile_list) holds part x of every region, regions in rank order, and is
 // drained in that order by the workgroups of XCD x (blockIdx.x % kXcds)
-// through the counter queue[x].  scratch: kRegionScratchInts(nregions) ints;
-// xcd_off and queue point into it (region_xcd_off, region_queue).
+// through the counter queue[kCounterStride x].  scratch:
+// kRegionScratchInts(nregions) ints; xcd_off and queue point into it
+// (region_xcd_off, region_queue).  Counters that many waves update sit
+// kCounterStride ints (256 bytes) apart: device-scope atomics on one line
+// from every XCD serialise.
 constexpr int kXcds = 8;
-__host__ __device__ constexpr int64_t kRegionScratchInts(int nregions) { return (int64_t)kXcds * nregions + 32; }
-__host__ __device__ inline int *region_xcd_off(int *scratch, int nregions) { return scratch + kXcds * nregions; }
-__host__ __device__ inline int *region_queue(int *scratch, int nregions) { return scratch + kXcds * nregions + 16; }
+constexpr int kCounterStride = 64;
+__host__ __device__ constexpr int64_t kRegionScratchInts(int nregions) {
+  return 16 + kCounterStride * kXcds + (int64_t)kXcds * nregions;
+}
+__host__ __device__ inline int *region_xcd_off(int *scratch, int) { return scratch; }
+__host__ __device__ inline int *region_queue(int *scratch, int) { return scratch + 16; }
+// where part x of the region at rank k starts in list x: [kXcds k + x]
+__host__ __device__ inline int *region_part_start(int *scratch, int) {
+  return scratch + 16 + kCounterStride * kXcds;
+}
 hipError_t launch_region_tiles(const LevelDesc &l, int R, int s, int E, int nry, int nregions,
                                const int *rank, int *tile_list, unsigned *region_left,
                                int *scratch, hipStream_t st);
 // Stores the GPU clock (100 MHz) in *out.
 hipError_t launch_stamp(uint64_t *out, hipStream_t st);
+// Waits about `us` microseconds on the GPU, then stores the clock in *out.
+hipError_t launch_wait_stamp(uint64_t *out, double us, hipStream_t st);
 
 }  // namespace pcrit

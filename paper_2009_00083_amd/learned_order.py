@@ -52,7 +52,7 @@ def training_set(field, *, ctx: Optional[B.Context] = None,
     return TrainingSet(X, y, level)
 
 
-def train(params, sets: Sequence[TrainingSet], *, steps: int = 300, lr: float = 3e-3,
+def train(params, sets: Sequence[TrainingSet], *, steps: int = 3000, lr: float = 1e-2,
           ctx: Optional[B.Context] = None) -> List[float]:
     """Full-batch Adam on the union of ``sets``; updates ``params`` in place
     and returns the mean loss before every step."""

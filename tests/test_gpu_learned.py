@@ -102,12 +102,13 @@ def test_backward_matches_oracle(ctx, dev, n):
     rng = np.random.default_rng(100 + n)
     p = (rng.standard_normal(pc.MLP_PARAMS) * 0.3).astype(np.float32)
     X, Xt = _inputs(dev, n, 50 + n)
-    y = rng.integers(0, 2, n).astype(np.uint8)
+    y = rng.integers(0, 256, n).astype(np.uint8)
+    y[: n // 3] = 0
     g, loss = pc.mlp_backward(torch.from_numpy(p).to(dev), Xt, torch.from_numpy(y).to(dev),
                               ctx=ctx)
     g = g.cpu().numpy().astype(np.float64)
-    ref = OL.backward(p, X, y)
-    lref = OL.loss_sum(p, X, y)
+    ref = OL.backward(p, X, y / 255.0)
+    lref = OL.loss_sum(p, X, y / 255.0)
     assert abs(float(loss.item()) - lref) <= 1e-4 * abs(lref) + 1e-5
     blocks = {"W1": (OL.OFF_W1, OL.OFF_B1), "b1": (OL.OFF_B1, OL.OFF_W2),
               "W2": (OL.OFF_W2, OL.OFF_B2), "b2": (OL.OFF_B2, OL.OFF_W3),
@@ -146,7 +147,7 @@ def test_training_lowers_loss(ctx, dev):
     assert losses[-1] < 0.8 * losses[0]
     # the loss the kernels report is the oracle's on the same parameters
     X = OL.bf16_bits_to_float(_bits(ts.X)).reshape(-1, 32)
-    y = ts.y.cpu().numpy()
+    y = ts.y.cpu().numpy() / 255.0
     g, loss = pc.mlp_backward(params, ts.X, ts.y, ctx=ctx)
     lref = OL.loss_sum(params.cpu().numpy(), X, y)
     assert abs(loss.item() - lref) <= 1e-4 * lref

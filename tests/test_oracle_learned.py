@@ -142,7 +142,8 @@ def test_linear_field_features():
 
 def test_labels_single_critical_vertex():
     """Codes all regular (0x09, 0x49 on the boundary) but one vertex p: only
-    the level vertex v with v - s/2 <= p < v + s/2 on every axis is 1."""
+    the level vertex v with v - s/2 <= p < v + s/2 on every axis is nonzero,
+    ceil(255 / volume of its clipped cell)."""
     shape = (10, 12, 17)
     rng = np.random.default_rng(4)
     for crit_code in (0x00, 0x12, 0x89):
@@ -161,8 +162,27 @@ def test_labels_single_critical_vertex():
                 inside = all((c + s // 2) // s <= d - 1 for c, d in zip(p, dims))
                 want = np.zeros(dims, np.uint8)
                 if inside:
-                    want[tuple(v)] = 1
+                    vol = 1
+                    for vc, n in zip(v, shape):
+                        vol *= min(vc * s + s - s // 2, n) - max(vc * s - s // 2, 0)
+                    want[tuple(v)] = math.ceil(255 / vol)
                 assert np.array_equal(lab, want.ravel()), (crit_code, p, level)
+
+
+def test_labels_fractions():
+    """All critical: 255 everywhere; every other x-column critical: cells of
+    an even number of columns hold exactly half (ceil(127.5) = 128)."""
+    shape = (9, 8, 16)
+    allc = np.zeros(shape, np.uint8)
+    for level in (0, 1, 2):
+        assert np.all(L.labels(allc, level) == 255)
+    half = np.full(shape, 0x09, np.uint8)
+    half[..., ::2] = 0x12
+    lab = L.labels(half, 2).reshape(3, 2, 4)
+    # x cells [4x - 2, 4x + 2) clipped: columns 0..1 for x = 0 (one even)
+    assert np.all(lab[..., 1:] == 128) and np.all(lab[..., 0] == 128)
+    lab0 = L.labels(half, 0).reshape(shape)
+    assert np.array_equal(lab0, np.where(half == 0x12, 255, 0))
 
 
 def test_region_scores_direct_count():
