@@ -283,7 +283,7 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
   }
 
   // Bitmask words: lane 16 k + 15 ends with word 4 tx + k of the row.
-  const int wshift = 4 * (lane & 15);
+  const int wshift = 4 * (lane & 7);
   const bool wlane = (lane & 15) == 15 && 4 * tp.tx + (lane >> 4) < g.rowwords;
   uint64_t *const wbase = g.bits + 4 * tp.tx + (lane >> 4);
   const unsigned vnib = (1u << nval) - 1u;  // valid columns of this lane
@@ -366,20 +366,21 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
             __builtin_amdgcn_raw_buffer_store_b8((unsigned char)code[e], crs, cvo[e],
                                                  (uint32_t)y * sy, 0);
         }
-        // this lane's four bits, moved to their place in the word of its
-        // sixteen-lane row and ORed across the row
+        // this lane's four bits, moved to their place in its half of the
+        // word of its sixteen-lane row; three DPP ORs gather lanes 0..7 of
+        // the row (the low half) in lane 7 and lanes 8..15 (the high half)
+        // in lane 15, and one more brings the low half to lane 15
         unsigned nib = 0;
 #pragma unroll
         for (int e = 0; e < 4; e++) nib |= (unsigned)cr[e] << e;
         if (!full) nib &= vnib;
-        uint64_t wv = (uint64_t)nib << wshift;
-        uint32_t wl = (uint32_t)wv, wh = (uint32_t)(wv >> 32);
-        static_for<4>([&](auto dc) {
+        uint32_t wv = nib << wshift;
+        static_for<3>([&](auto dc) {
           constexpr int d = 1 << decltype(dc)::value;
-          wl |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wl, 0x110 + d, 0xF, 0xF, true);
-          wh |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wh, 0x110 + d, 0xF, 0xF, true);
+          wv |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wv, 0x110 + d, 0xF, 0xF, true);
         });
-        if (wlane) wbase[((int64_t)z * my + y) * g.rowwords] = ((uint64_t)wh << 32) | wl;
+        const uint32_t wlo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wv, 0x118, 0xF, 0xF, true);
+        if (wlane) wbase[((int64_t)z * my + y) * g.rowwords] = ((uint64_t)wv << 32) | wlo;
       }
     });
   };
