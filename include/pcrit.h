@@ -29,8 +29,9 @@
  *   - the field is float32, C order [z][y][x] (x fastest), nx*ny*nz
  *     samples; nz == 1 selects the 2D triangulation;
  *   - every active axis needs >= 2 samples and nx*ny*nz <= 2^32 - 1; a
- *     plane must hold at most 2^30 samples (nx*ny in 3D, nx in 2D), since
- *     the kernels address it with 32-bit byte offsets;
+ *     plane must hold at most 2^30 - 1 samples (nx*ny in 3D, nx in 2D):
+ *     the kernels address it through buffer descriptors whose byte range
+ *     ends at 2^32 - 1;
  *   - the caller owns and frees every buffer it passes in; the context owns
  *     only its lookup tables, scratch and events;
  *   - a call returns PCRIT_OK or a negative status; argument errors are
@@ -61,7 +62,7 @@ extern "C" {
 #define PCRIT_OK 0
 #define PCRIT_E_ARG (-1)      /* NULL/misaligned pointer, bad argument */
 #define PCRIT_E_DIMS (-2)     /* an active axis < 2 samples, N >= 2^32, or a
-                                 plane of more than 2^30 samples */
+                                 plane of 2^30 samples or more */
 #define PCRIT_E_LEVEL (-3)    /* 2^level > n-1 on some active axis */
 #define PCRIT_E_CAPACITY (-4) /* critical list larger than its capacity */
 #define PCRIT_E_NAN (-5)      /* a sample of the level is NaN */

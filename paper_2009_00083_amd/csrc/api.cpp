@@ -41,8 +41,9 @@ int check_dims(int64_t nx, int64_t ny, int64_t nz) {
     return PCRIT_E_DIMS;
   const double n = (double)nx * (double)ny * (double)nz;
   if (n > 4294967295.0) return PCRIT_E_DIMS;
-  // the kernels address a plane (3D) or a row (2D) with 32-bit byte offsets
-  if ((nz > 1 ? (double)nx * (double)ny : (double)nx) > 1073741824.0)
+  // the kernels address a plane (3D) or a row (2D) through buffer
+  // descriptors whose byte range ends at 2^32 - 1: at most 2^30 - 1 samples
+  if ((nz > 1 ? (double)nx * (double)ny : (double)nx) > 1073741823.0)
     return PCRIT_E_DIMS;
   return PCRIT_OK;
 }

@@ -131,3 +131,77 @@ def test_max_size(shape, windows):
     del p, r1, ft
     ctx.close()
     torch.cuda.empty_cache()
+
+
+def _check_window_mid(ft, codes, crit, n, a, b):
+    """Codes and list entries of the index range [a, b) of the middle axis
+    (rows of a two-plane 3D grid, columns of a two-row 2D grid) against the
+    oracle, which classifies that range plus one neighbour per side.  The
+    sub-grid keeps the lexicographic order of the vertices, so the tie-break
+    is the same; its extra rows (columns) are not compared."""
+    three = ft.dim() == 3
+    lo, hi = max(a - 1, 0), min(b + 1, ft.shape[-2] if three else ft.shape[-1])
+    sub = (ft[:, lo:hi, :] if three else ft[:, lo:hi]).contiguous().cpu().numpy()
+    ref = oracle.classify(sub)
+    assert ref.status == 0
+    got_codes = (codes[:, a:b, :] if three else codes[:, a:b]).cpu().numpy()
+    want_codes = ref.codes[:, a - lo:b - lo, :] if three else ref.codes[:, a - lo:b - lo]
+    assert np.array_equal(got_codes, want_codes)
+    # list entries: one run per plane (3D) or row (2D)
+    nx = ft.shape[-1]
+    outer = ft.shape[0]
+    inner = ft.shape[1] * nx if three else nx        # vertices per plane / row
+    unit = nx if three else 1                         # index step of the middle axis
+    sub_inner = (hi - lo) * unit
+    ref_idx = ref.crit.astype(np.int64)
+    total = 0
+    for o in range(outer):
+        g0, g1 = o * inner + a * unit, o * inner + b * unit
+        start = _count_below(crit, n, g0)
+        stop = _count_below(crit, n, g1)
+        got = crit[start:stop].cpu().numpy().view(np.uint32).astype(np.int64)
+        s0, s1 = o * sub_inner + (a - lo) * unit, o * sub_inner + (b - lo) * unit
+        sel = ref_idx[(ref_idx >= s0) & (ref_idx < s1)]
+        want = sel - o * sub_inner - (a - lo) * unit + g0
+        assert np.array_equal(got, want)
+        total += len(got)
+    return total
+
+
+@pytest.mark.parametrize("shape,windows", [
+    # planes of 2^30 - 4 vertices (the byte range of a buffer descriptor
+    # ends at 2^32 - 1), 24940 = 4 * 5 * 29 * 43 columns (the quad tiles) by
+    # 43053 = 3 * 113 * 127 rows; the last window ends at the last vertex
+    ((2, 43053, 24940), [(21520, 21530), (43045, 43053)]),
+    # a 2D row of 2^30 - 1 vertices, the largest accepted
+    ((2, (1 << 30) - 1), [(1 << 29, (1 << 29) + 4096), ((1 << 30) - 4097, (1 << 30) - 1)]),
+])
+def test_plane_and_row_limit(shape, windows):
+    n_all = int(np.prod(shape))
+    assert n_all > (1 << 31) - (1 << 17)
+    dev = torch.device("cuda:0")
+    ctx = pc.Context(0)
+    log("plane / row limit", shape)
+    ft = fieldgen.device_iid_field(shape, 23, dev)
+    r = pc.classify(ft, ctx=ctx, with_crit_codes=True)
+    torch.cuda.synchronize()
+    n = r.count
+    log("critical", n, "of", n_all)
+    assert n == _critical_codes(r.codes)
+    _check_ascending(r.crit, n)
+    assert int(_u32(r.crit[n - 1:n])) >= n_all - (1 << 16)
+    for s in range(0, n, CH):
+        idx = _u32(r.crit[s:min(n, s + CH)])
+        want = r.codes.reshape(-1)[idx]
+        assert torch.equal(r.crit_codes[s:min(n, s + CH)], want)
+    for a, b in windows:
+        log("window", a, b)
+        assert _check_window_mid(ft, r.codes, r.crit, n, a, b) > 0
+    p = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    assert p.status == 0 and p.levels == [0]
+    assert torch.equal(p.codes, r.codes)
+    assert torch.equal(p.level_list(0), r.crit[:n])
+    del r, p, ft
+    ctx.close()
+    torch.cuda.empty_cache()

@@ -552,18 +552,24 @@ def test_full_size(ctx, dev, name):
     f = fieldgen.config_field(name, device="cuda")
     ft = torch.from_numpy(f).to(dev)
     log("direct", name)
-    r = pc.classify(ft, ctx=ctx)
+    r = pc.classify(ft, ctx=ctx, with_crit_codes=True)
     torch.cuda.synchronize()
     ref = oracle.classify(f)
     log("oracle done; critical fraction", ref.count / f.size)
     assert_same(f, 0, r, ref, name)
-    p = pc.progressive(ft, ctx=ctx)
+    ref_flat = ref.codes.ravel()
+    assert np.array_equal(r.crit_codes[:r.count].cpu().numpy(), ref_flat[ref.crit])
+    p = pc.progressive(ft, ctx=ctx, with_crit_codes=True)
     torch.cuda.synchronize()
     assert torch.equal(p.codes, r.codes)
     crit_all = p.crit.cpu().numpy().view(np.uint32)
+    ccodes_all = p.crit_codes.cpu().numpy()
     for i, k in enumerate(p.levels):
         lref = ref if k == 0 else oracle.classify(f, level=k)
-        assert np.array_equal(crit_all[p.offsets[i]:p.offsets[i + 1]], lref.crit), k
+        a, b = p.offsets[i], p.offsets[i + 1]
+        assert np.array_equal(crit_all[a:b], lref.crit), k
+        # list codes of every level (level k's own classification)
+        assert np.array_equal(ccodes_all[a:b], lref.codes.ravel()[lref.crit]), k
         if 0 < k <= 2:
             d = gpu_classify(ctx, dev, f, k)
             assert_same(f, k, d, lref, f"{name} level {k}")

@@ -96,16 +96,17 @@ def test_level_geometry_matches_oracle(oracle_mod, shape):
 
 
 def test_bad_dims_rejected():
-    # (z, y, x) / (y, x): a missing axis, N >= 2^32, a plane or row of more
-    # than 2^30 samples
+    # (z, y, x) / (y, x): a missing axis, N >= 2^32, a plane or row of 2^30
+    # samples or more
     for shape in [(5, 5, 1), (5, 1, 5), (4, 1), (1, 7), (1 << 17, 1 << 16, 2),
-                  (2, (1 << 15) + 1, 1 << 15), (2, (1 << 30) + 1)]:
+                  (2, 1 << 15, 1 << 15), (2, 1 << 30)]:
         with pytest.raises(pc.PcritError) as e:
             pc.max_level(shape)
         assert e.value.status == pc.E_DIMS
-    # the largest accepted plane / row
-    assert pc.max_level((2, 1 << 15, 1 << 15)) == 0
-    assert pc.max_level((3, 1 << 30)) == 1
+    # the largest accepted planes / rows
+    assert pc.max_level((2, (1 << 15) - 1, 1 << 15)) == 0
+    assert pc.max_level((2, 1 << 15, (1 << 15) - 1)) == 0
+    assert pc.max_level((3, (1 << 30) - 1)) == 1
 
 
 def _greedy_f1(shape, level, p, pcode, e, ecode):
