@@ -376,6 +376,42 @@ int pcrit_progressive_timeline(pcrit_ctx *ctx, void *hip_stream, const float *fi
                                const float *mlp_params, int64_t *level_offsets_host,
                                double *level_ms_host, double *region_ms_host);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent fields (the scope table's second "next" row).
+ *
+ * Every field of the batch is classified at level 0 exactly as
+ * pcrit_classify would (Section 3.1, ties by index within the field), but
+ * groups of up to 16 fields share one classification launch and one
+ * compaction launch, so many small fields do not pay a launch pair each.
+ * ---------------------------------------------------------------------- */
+#define PCRIT_MAX_BATCH_FIELDS (1 << 20)
+
+typedef struct pcrit_batch_field {
+  const float *field;  /* device, float32 C order [z][y][x], 4-byte aligned */
+  int64_t nx, ny, nz;  /* as for pcrit_classify; nz == 1: 2D */
+  uint8_t *codes;      /* device, nx*ny*nz bytes (written at every vertex) */
+} pcrit_batch_field;
+
+/* Classify n_fields fields (1 .. PCRIT_MAX_BATCH_FIELDS, all 3D or all 2D,
+ * else PCRIT_E_ARG) described by fields_host (host array).
+ *   crit, crit_codes, crit_capacity  one list for the whole batch: field i's
+ *                     ascending critical indices (field-local, uint32) are
+ *                     crit[off[i] .. off[i+1]); entries past the capacity
+ *                     are not written; crit_codes may be NULL
+ *   offsets_dev       device, n_fields+1 int64, or NULL: the list offsets,
+ *                     written on the stream (off[0] = 0)
+ *   offsets_host      host, n_fields+1 int64, or NULL: non-NULL makes the
+ *                     call wait for the stream and copy the offsets
+ * Errors: as pcrit_classify for each field's sizes (the first failing
+ * field's status); with offsets_host, PCRIT_E_NAN if any field has a NaN
+ * sample and PCRIT_E_CAPACITY if off[n_fields] > crit_capacity (the
+ * offsets then hold the required sizes).  Clears off[0] with a memset on the
+ * stream (not for graph capture); calls that overlap on one context race. */
+int pcrit_classify_batch(pcrit_ctx *ctx, void *hip_stream, int n_fields,
+                         const pcrit_batch_field *fields_host, uint32_t *crit,
+                         uint8_t *crit_codes, int64_t crit_capacity,
+                         int64_t *offsets_host, int64_t *offsets_dev);
+
 #ifdef __cplusplus
 }
 #endif

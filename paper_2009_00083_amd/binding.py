@@ -31,7 +31,8 @@ EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_set_kernel_timing", "pcrit_kernel_ms", "pcrit_preview_f1",
             "pcrit_preview_f1_levels", "pcrit_mlp_feature_level", "pcrit_mlp_features",
             "pcrit_mlp_labels", "pcrit_mlp_forward", "pcrit_mlp_backward",
-            "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline")
+            "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline",
+            "pcrit_classify_batch")
 MLP_PARAMS = 6337
 MLP_INPUTS = 32
 
@@ -74,6 +75,8 @@ def _load():
     lib.pcrit_classify.restype = i32
     lib.pcrit_classify_noalloc.argtypes = lib.pcrit_classify.argtypes
     lib.pcrit_classify_noalloc.restype = i32
+    lib.pcrit_classify_batch.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp]
+    lib.pcrit_classify_batch.restype = i32
     lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
     lib.NULL_CB = ctypes.cast(None, lib.LEVEL_CB)
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
@@ -332,6 +335,66 @@ def classify(field, level: int = 0, *, ctx: Optional[Context] = None,
     k = max(0, min(n, capacity))
     return ClassifyResult(codes, crit[:k], None if cc is None else cc[:k], n,
                           st)
+
+
+class _BatchField(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_void_p), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("codes", ctypes.c_void_p)]
+
+
+@dataclass
+class BatchResult:
+    codes: List["object"]      # per field: uint8 tensor, full resolution
+    crit: "object"             # int32 tensor: the lists of all fields
+    crit_codes: "object"       # uint8 tensor or None
+    offsets: np.ndarray        # n_fields + 1: field i's list is crit[off[i]:off[i+1]]
+    status: int
+
+    def field_list(self, i: int):
+        return self.crit[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+
+def classify_batch(fields, *, ctx: Optional[Context] = None, capacity: Optional[int] = None,
+                   with_crit_codes: bool = False, codes=None, crit=None, offsets_dev=None,
+                   stream=None, check: bool = True) -> BatchResult:
+    """Classify a list of fields (all 3D or all 2D, level 0) with shared
+    launches.  With ``offsets_dev`` (int64 device tensor of n+1 elements)
+    the call is asynchronous: offsets land there and ``offsets`` is None."""
+    import torch
+    if len(fields) < 1:
+        raise PcritError(E_ARG, "empty batch")
+    dev = fields[0].device
+    lib = _load()
+    c = _ctx_for(fields[0], ctx)
+    descs = (_BatchField * len(fields))()
+    total = 0
+    out_codes = []
+    for i, f in enumerate(fields):
+        if f.device != dev:
+            raise PcritError(E_ARG, "fields on different devices")
+        nx, ny, nz = _check_field(f)
+        cd = codes[i] if codes is not None else torch.zeros(f.shape, dtype=torch.uint8,
+                                                             device=dev)
+        check_buffer(f"codes[{i}]", cd, torch.uint8, dev, numel=f.numel())
+        descs[i] = _BatchField(f.data_ptr(), nx, ny, nz, cd.data_ptr())
+        out_codes.append(cd)
+        total += f.numel()
+    capacity = _capacity(capacity, crit, total)
+    if crit is None:
+        crit = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    check_buffer("crit", crit, torch.int32, dev, min_numel=capacity)
+    cc = (torch.empty(max(capacity, 1), dtype=torch.uint8, device=dev)
+          if with_crit_codes else None)
+    if offsets_dev is not None:
+        check_buffer("offsets_dev", offsets_dev, torch.int64, dev, min_numel=len(fields) + 1)
+    offs = None if offsets_dev is not None else np.zeros(len(fields) + 1, np.int64)
+    st = lib.pcrit_classify_batch(
+        c.handle, _stream_handle(fields[0], stream), len(fields), ctypes.addressof(descs),
+        _ptr(crit), _ptr(cc), int(capacity), None if offs is None else offs.ctypes.data,
+        _ptr(offsets_dev))
+    if check and st not in (0, E_CAPACITY):
+        raise PcritError(st, "pcrit_classify_batch")
+    return BatchResult(out_codes, crit, cc, offs, st)
 
 
 def classify_noalloc(field, level: int, codes, crit, *, ctx: Context,

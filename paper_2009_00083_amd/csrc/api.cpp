@@ -114,6 +114,8 @@ struct pcrit_ctx {
   hipEvent_t last_kev = nullptr;
   void *tl = nullptr;  // region timeline and learned-order scratch
   int64_t tl_bytes = 0;
+  int64_t *boff = nullptr;  // list offsets of a batch (when the caller gives none)
+  int64_t boff_bytes = 0;
   // second stream (default priority) on which the learned order is scored
   // while the leading levels run, and the events that fork and join it
   hipStream_t side = nullptr;
@@ -168,6 +170,11 @@ void record_kernel(pcrit_ctx *c, int which, int level, int end, hipStream_t st) 
 // One level of a launch.
 struct Step {
   Geom g;
+  // batches: this step's own field and codes (else the call's), and every
+  // step writes its codes
+  const float *f = nullptr;
+  uint8_t *codes = nullptr;
+  bool batch = false;
   const Geom *prev = nullptr;  // previous (coarser) level, progressive only
   bool dirty = false;          // test old vertices against `prev`
   int mask_read = -1;          // masks slot holding prev's masks, or -1
@@ -217,7 +224,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
                   unsigned gen, bool final_group, uint64_t *bits, int *counts,
                   int64_t *publish = nullptr, int publish_n = 0,
-                  const RegionHooks *rh = nullptr) {
+                  const RegionHooks *rh = nullptr, int64_t *lbase = nullptr) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -225,8 +232,6 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   const bool small = small_chunks(total_words);
   const int64_t cw = small ? kSmallChunkWords : kChunkWords;
   ClassifyArgs a{};
-  a.f = field;
-  a.codes = codes;
   a.lut = dim == 3 ? c->lut3 : c->lut2;
   a.nl = n;
   a.reclass_acc = c->reclass_acc;
@@ -241,6 +246,8 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     const Geom &g = sp.g;
     const bool last = l == n - 1;
     LevelDesc &d = a.lv[l];
+    d.f = sp.f ? sp.f : field;
+    d.codes = sp.codes ? sp.codes : codes;
     d.sx = g.s;
     d.sy = g.s * g.nx;
     d.sz = g.s * g.nx * g.ny;
@@ -255,7 +262,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     d.tile_begin = tiles;
     tiles += d.ntiles;
     d.bits = bits + woff;
-    d.lcodes = fused && !last && crit_codes ? c->lcodes + loff : nullptr;
+    d.lcodes = fused && !last && crit_codes && !sp.batch ? c->lcodes + loff : nullptr;
     if (!fused && sp.mask_read >= 0) d.prev_masks = c->masks[sp.mask_read];
     if (sp.prev) {
       d.pmx = (int)sp.prev->mx;
@@ -265,10 +272,13 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     // full-resolution codes: the last level of the call writes every code
     // (a vertex's code at its finest level); earlier levels only when their
     // lists carry codes
-    d.write_codes = (!fused || last) && (final_group || crit_codes != nullptr);
+    d.write_codes = sp.batch || ((!fused || last) && (final_group || crit_codes != nullptr));
     d.dirty = sp.dirty;
 
     CompactLevel &q = b.lv[l];
+    q.codes = d.codes;
+    q.nx = g.nx;
+    q.ny = g.ny;
     q.bits = d.bits;
     q.words = g.words;
     q.rowwords = (int)g.rowwords;
@@ -326,13 +336,10 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   record_kernel(c, 0, tlevel, 1, st);
 
   b.nchunks = (int)chunks;
-  b.nx = s0.g.nx;
-  b.ny = s0.g.ny;
   b.crit = crit;
   b.crit_codes = crit_codes;
-  b.codes = codes;
   b.cap = cap;
-  b.level_base = c->level_base;
+  b.level_base = lbase ? lbase : c->level_base;
   b.count_dev = count_dev;
   b.publish = publish;
   b.publish_n = publish_n;
@@ -467,6 +474,7 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->masks[1]);
   hipFree(c->reclass_acc);
   hipFree(c->tl);
+  hipFree(c->boff);
   hipFree(c->status);
   if (c->side) hipStreamDestroy(c->side);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
@@ -1097,4 +1105,72 @@ int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *fiel
   return c->h_base[kmax + 1] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
 
+
+// ------------------------------------------------------------------------
+// Batches of independent fields (level 0): groups of up to kMaxFused fields
+// share one classification and one compaction launch; every field keeps its
+// own pointers and sizes, and the lists land in field order.
+int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
+                         const pcrit_batch_field *fields_host, uint32_t *crit,
+                         uint8_t *crit_codes, int64_t crit_capacity, int64_t *offsets_host,
+                         int64_t *offsets_dev) {
+  if (!c || n_fields < 1 || n_fields > PCRIT_MAX_BATCH_FIELDS || !fields_host || crit_capacity < 0 ||
+      (crit_capacity > 0 && !crit) || (crit && misaligned(crit, 4)) ||
+      (offsets_dev && misaligned(offsets_dev, 8)))
+    return PCRIT_E_ARG;
+  std::vector<Step> steps((size_t)n_fields);
+  int dim = 0;
+  int64_t words = 0, chunks = 0;
+  for (int i = 0; i < n_fields; i++) {
+    const pcrit_batch_field &fd = fields_host[i];
+    if (!fd.field || !fd.codes || misaligned(fd.field, 4)) return PCRIT_E_ARG;
+    Geom g;
+    const int st = make_geom(fd.nx, fd.ny, fd.nz, 0, &g);
+    if (st) return st;
+    if (dim == 0) dim = g.dim;
+    if (g.dim != dim) return PCRIT_E_ARG;  // one triangulation per call
+    Step &sp = steps[(size_t)i];
+    sp.g = g;
+    sp.f = fd.field;
+    sp.codes = fd.codes;
+    sp.batch = true;
+    sp.slot = i;
+  }
+  // scratch for the largest group
+  for (int i0 = 0; i0 < n_fields; i0 += kMaxFused) {
+    const int n = std::min(kMaxFused, n_fields - i0);
+    int64_t w, ch, lb;
+    launch_needs(&steps[(size_t)i0], n, false, &w, &ch, &lb);
+    words = std::max(words, w);
+    chunks = std::max(chunks, ch);
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  hipStream_t s = (hipStream_t)hip_stream;
+  int st = ensure((void **)&c->bits, &c->bits_words, words * 8);
+  if (!st) st = ensure((void **)&c->counts, &c->counts_n, chunks * (int64_t)sizeof(int));
+  int64_t *off = offsets_dev;
+  if (!st && !off) {
+    st = ensure((void **)&c->boff, &c->boff_bytes, 8 * (int64_t)(n_fields + 1));
+    off = c->boff;
+  }
+  if (st) return st;
+  // the first group's lists start at off[0] = 0
+  if (hipMemsetAsync(off, 0, sizeof(int64_t), s) != hipSuccess) return PCRIT_E_HIP;
+  const unsigned gen = next_gen(c);
+  reset_kernel_marks(c);
+  for (int i0 = 0; i0 < n_fields; i0 += kMaxFused) {
+    const int n = std::min(kMaxFused, n_fields - i0);
+    st = enqueue_group(c, s, steps[(size_t)i0].f, &steps[(size_t)i0], n, steps[(size_t)i0].codes,
+                       crit, crit_codes, crit_capacity, nullptr, gen, true, c->bits, c->counts,
+                       nullptr, 0, nullptr, off);
+    if (st) return st;
+  }
+  if (!offsets_host) return PCRIT_OK;
+  if (hipMemcpyAsync(offsets_host, off, 8 * (size_t)(n_fields + 1), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      read_status(c, s))
+    return PCRIT_E_HIP;
+  if (c->h_flags[0] == gen) return PCRIT_E_NAN;
+  return offsets_host[n_fields] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
+}
 }  // extern "C"

@@ -233,7 +233,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
   // never used).
   static_assert(NR <= 16, "packed halo within one DPP row");
   const int xc = min(x, mx - 1);
-  const char *fb = reinterpret_cast<const char *>(a.f);
+  const char *fb = reinterpret_cast<const char *>(g.f);
   const int64_t szb = g.sz * 4;
   uint32_t voff[NR];
 #pragma unroll
@@ -503,7 +503,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
     // plane of codes is < 4 GiB and a group spans at most four rows)
     const int qs = lane >> 4;
     const uint32_t loff = (uint32_t)((qs / R) * g.sz + (qs % R) * g.sy) + 4u * (lane & 15);
-    const uint8_t *cb = a.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy + x0;
+    const uint8_t *cb = g.codes + (int64_t)z0 * g.sz + (int64_t)y0 * g.sy + x0;
 #pragma unroll 4
     for (int k = 0; k < NQ / 4; k++) {
       if (k * PG >= nzl) break;
@@ -525,7 +525,7 @@ __device__ __forceinline__ void tile3d(const ClassifyArgs &a,
       for (int j = 0; j < nyl; j++) {
         const unsigned b = stc[(zz * R + j) * 64 + lane];
         if (full_res)
-          st_u8(rsrc(a.codes + (int64_t)(z0 + zz) * g.sz + (int64_t)(y0 + j) * g.sy), xoffc, b);
+          st_u8(rsrc(g.codes + (int64_t)(z0 + zz) * g.sz + (int64_t)(y0 + j) * g.sy), xoffc, b);
         if (g.lcodes)
           st_u8(rsrc(g.lcodes + ((int64_t)(z0 + zz) * my + (y0 + j)) * mx), (uint32_t)x, b);
       }
@@ -606,7 +606,7 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
   const int xh = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + 64, mx - 1) : xc);
   const uint32_t xoff = (uint32_t)((int64_t)xc * g.sx * 4);
   const uint32_t hoff = (uint32_t)((int64_t)xh * g.sx * 4);
-  const char *fb = reinterpret_cast<const char *>(a.f);
+  const char *fb = reinterpret_cast<const char *>(g.f);
   const int64_t syb = g.sy * 4;
   const char *pmb = reinterpret_cast<const char *>(g.prev_masks);
   const uint32_t pmx_off = RP ? (uint32_t)min(xc >> 1, g.pmx - 1) : 0u;
@@ -663,7 +663,7 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
     if ((RP || FAR) && even && dirty_test) {
       unsigned pm = 0;
       if (RP) pm = mid.pm;
-      if (FAR && !RP && out_lane && !(x & 1)) pm = far_mask2(a.f, g, x, y, c);
+      if (FAR && !RP && out_lane && !(x & 1)) pm = far_mask2(g.f, g, x, y, c);
       bool d;
       if (MODE != 0) {
         d = m != pm;  // both are 6-bit masks
@@ -725,7 +725,7 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
     }
   };
   const bool codes4 = g.write_codes && g.sx == 1 && full_tile && !(g.sy & 3);
-  if (codes4) rows4(stc, a.codes + (int64_t)y0 * g.sy + x0, g.sy);
+  if (codes4) rows4(stc, g.codes + (int64_t)y0 * g.sy + x0, g.sy);
   const bool masks4 = WM && store_masks && full_tile && !(mx & 3);
   if (masks4) rows4(stm, reinterpret_cast<uint8_t *>(g.masks) + (int64_t)y0 * mx + x0, mx);
   if (!out_lane) return;
@@ -736,7 +736,7 @@ __device__ __forceinline__ void tile2d(const ClassifyArgs &a,
 #pragma unroll 1
     for (int q = 0; q < nrows; q++) {
       const unsigned b = stc[q * 64 + lane];
-      if (codes1) st_u8(rsrc(a.codes + (int64_t)(y0 + q) * g.sy), xoffc, b);
+      if (codes1) st_u8(rsrc(g.codes + (int64_t)(y0 + q) * g.sy), xoffc, b);
       if (g.lcodes) st_u8(rsrc(g.lcodes + (int64_t)(y0 + q) * mx), (uint32_t)x, b);
       if (masks1)
         st_u8(rsrc(reinterpret_cast<uint8_t *>(g.masks) + (int64_t)(y0 + q) * mx),
@@ -998,7 +998,7 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
   }
 
   const bool linear = L.linear && !a.crit_codes;
-  const int64_t rowstep = L.s * a.nx;
+  const int64_t rowstep = L.s * L.nx;
   const uint32_t s = (uint32_t)L.s;
   uint16_t *went = s_ent[w];
   int64_t out0 = base + prefix + woff;  // list position of the round's first entry
@@ -1015,7 +1015,7 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
       const uint32_t r = gw / (uint32_t)L.rowwords;
       const uint32_t xw = gw - r * (uint32_t)L.rowwords;
       const uint32_t zz = r / (uint32_t)L.my, yy = r - zz * (uint32_t)L.my;
-      s_row0[w][lane] = (uint32_t)(rowstep * ((int64_t)yy + a.ny * (int64_t)zz) +
+      s_row0[w][lane] = (uint32_t)(rowstep * ((int64_t)yy + L.ny * (int64_t)zz) +
                                    L.s * (int64_t)xw * kTileCols);
     }
     {
@@ -1058,12 +1058,12 @@ __global__ __launch_bounds__(kCompactThreads) void expand_kernel(CompactArgs a) 
           uint8_t code;
           if (L.lcodes) {
             // dense level index from the full-resolution one
-            const uint32_t xf = idx % (uint32_t)a.nx, rest = idx / (uint32_t)a.nx;
-            const uint32_t yf = rest % (uint32_t)a.ny, zf = rest / (uint32_t)a.ny;
+            const uint32_t xf = idx % (uint32_t)L.nx, rest = idx / (uint32_t)L.nx;
+            const uint32_t yf = rest % (uint32_t)L.ny, zf = rest / (uint32_t)L.ny;
             const int64_t lix = ((int64_t)(zf / s) * L.my + yf / s) * L.mx + xf / s;
             code = L.lcodes[lix];
           } else {
-            code = a.codes[idx];
+            code = L.codes[idx];
           }
           a.crit_codes[out0 + e] = code;
         }

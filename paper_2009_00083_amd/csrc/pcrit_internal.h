@@ -105,6 +105,8 @@ constexpr int kMaxFused = 16;
 
 // One level as the classification kernels see it.
 struct LevelDesc {
+  const float *f;         // full-resolution field of this level
+  uint8_t *codes;         // its full-resolution code bytes
   int64_t sx, sy, sz;     // element strides of one level step along x, y, z
   int mx, my, mz;         // level sizes (mz = 1 in 2D)
   int rowwords;           // ceil(mx / 64)
@@ -126,8 +128,6 @@ struct LevelDesc {
 };
 
 struct ClassifyArgs {
-  const float *f;       // full-resolution field
-  uint8_t *codes;       // full-resolution code bytes
   const uint8_t *lut;   // link-pattern table (device)
   int nl;               // levels in this launch (1, or several when fused)
   int ntiles;           // wave tiles of all levels
@@ -139,6 +139,8 @@ struct ClassifyArgs {
 
 // One level as the compaction kernels see it.
 struct CompactLevel {
+  const uint8_t *codes;   // full-resolution codes of this level's grid
+  int64_t nx, ny;         // full-resolution sizes of this level's grid
   const uint64_t *bits;
   int64_t words;        // rows * rowwords
   int rowwords, mx, my;
@@ -154,10 +156,8 @@ struct CompactArgs {
   int nl;
   int nchunks;          // chunks of all levels
   CompactLevel lv[kMaxFused];
-  int64_t nx, ny;       // full-resolution sizes
   uint32_t *crit;
   uint8_t *crit_codes;  // may be null
-  const uint8_t *codes; // full-resolution codes (levels without lcodes)
   int64_t cap;
   int64_t *level_base;  // list offsets; [0] is 0
   int64_t *count_dev;   // may be null: total of the last level
