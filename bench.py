@@ -15,8 +15,10 @@ against the exact list at 10, 25, 50, 75 and 90 % of the plain call's time
 to exact, for the
 plain level order, for region-by-region refinement in region id order and
 in the learned order (the order network trained, untimed, on held-out
-fields), on this field and on the smooth recipe at 512^3; the direct level-0
-rate; per-level rates; the roofline of the dominant kernel; and the CPU
+fields), on this field and on the smooth recipe at 512^3; "batch": 200
+independent fields of 33..257 samples per axis classified with shared
+launches against one call per field; the direct level-0 rate; per-level
+rates; the roofline of the dominant kernel; and the CPU
 oracle's rate on bounded samples of the same workload (all threads of this
 process's share, and one thread).
 """
@@ -109,6 +111,81 @@ def train_order_network(pc, ctx, dev, steps=3000):
     return params, sets[0].level, losses
 
 
+BATCH_FIELDS = 200
+BATCH_AXIS = (33, 257)
+
+
+def batch_measure(pc, ctx, dev, reps=10):
+    """Batched classification of many independent fields against one call
+    per field: 200 3D fields, every axis drawn from U{33..257} (seed 5),
+    each 8 Gaussians (the small-field recipe without noise), resident on the
+    GPU; every way enqueued back to back with device-side counts; the
+    batched call also as a replayed HIP graph."""
+    import torch
+    import fieldgen
+    rng = np.random.default_rng(5)
+    ts = []
+    for i in range(BATCH_FIELDS):
+        shape = tuple(int(v) for v in rng.integers(BATCH_AXIS[0], BATCH_AXIS[1] + 1, size=3))
+        f = fieldgen.gaussian_field(shape, 1000 + i, 8, device="cuda")
+        ts.append(torch.from_numpy(f).to(dev))
+    nv = sum(t.numel() for t in ts)
+    codes = [torch.empty(t.shape, dtype=torch.uint8, device=dev) for t in ts]
+    crit = torch.empty(nv, dtype=torch.int32, device=dev)
+    offs = torch.empty(BATCH_FIELDS + 1, dtype=torch.int64, device=dev)
+    ref = pc.classify_batch(ts, ctx=ctx, codes=codes, crit=crit)
+    # one call per field into its own slice of the same list buffer
+    counts = torch.empty(BATCH_FIELDS, dtype=torch.int64, device=dev)
+    starts = np.concatenate([[0], np.cumsum([t.numel() for t in ts])])
+    crit1 = torch.empty(nv, dtype=torch.int32, device=dev)
+
+    def per_field():
+        for i, t in enumerate(ts):
+            pc.classify(t, ctx=ctx, codes=codes[i], crit=crit1[int(starts[i]):int(starts[i + 1])],
+                        count_dev=counts[i:i + 1])
+
+    def batched():
+        pc.classify_batch(ts, ctx=ctx, codes=codes, crit=crit, offsets_dev=offs)
+
+    for fn in (per_field, batched):
+        fn()
+    torch.cuda.synchronize()
+    # the same lists both ways
+    cnt = counts.cpu().numpy()
+    for i in (0, BATCH_FIELDS // 2, BATCH_FIELDS - 1):
+        a = ref.field_list(i)
+        assert int(cnt[i]) == a.numel()
+        assert torch.equal(crit1[int(starts[i]):int(starts[i]) + a.numel()], a)
+    # the batched call captured once in a graph and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batched()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched()
+    graph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(offs.cpu(), torch.from_numpy(ref.offsets))
+    out = {}
+    for name, fn in (("per_field", per_field), ("batched", batched),
+                     ("batched_graph", graph.replay)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[name + "_ms"] = round(ms, 3)
+        out[name + "_gvps"] = round(nv / (ms * 1e-3) / 1e9, 2)
+    out.update({"fields": BATCH_FIELDS, "axis": list(BATCH_AXIS), "vertices": int(nv),
+                "critical": int(ref.offsets[-1]),
+                "speedup": round(out["per_field_ms"] / out["batched_ms"], 2)})
+    return out
+
+
 def _region_of(points, shape, edge):
     nz, ny, nx = shape
     nry = -(-ny // edge)
@@ -197,6 +274,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched many-field measurement")
     ap.add_argument("--no-preview", action="store_true",
                     help="skip the preview-quality passes (and the order "
                          "network's training)")
@@ -407,6 +486,9 @@ def main():
             "algorithmic_bytes": alg_bytes,
         },
     }
+
+    if not args.no_batch:
+        out["batch"] = batch_measure(pc, ctx, dev)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -405,8 +405,10 @@ typedef struct pcrit_batch_field {
  * Errors: as pcrit_classify for each field's sizes (the first failing
  * field's status); with offsets_host, PCRIT_E_NAN if any field has a NaN
  * sample and PCRIT_E_CAPACITY if off[n_fields] > crit_capacity (the
- * offsets then hold the required sizes).  Clears off[0] with a memset on the
- * stream (not for graph capture); calls that overlap on one context race. */
+ * offsets then hold the required sizes).  Without offsets_host the call
+ * launches kernels only (no allocation once the context's scratch has grown
+ * to the batch, no memset, no wait), so it can be captured in a HIP graph;
+ * calls that overlap on one context race (they share its scratch). */
 int pcrit_classify_batch(pcrit_ctx *ctx, void *hip_stream, int n_fields,
                          const pcrit_batch_field *fields_host, uint32_t *crit,
                          uint8_t *crit_codes, int64_t crit_capacity,

@@ -255,6 +255,10 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     d.my = (int)g.my;
     d.mz = (int)g.mz;
     d.rowwords = (int)g.rowwords;
+    // batches run as fused launches too (their steps test no old vertices):
+    // measured on 200 fields of 33..257 samples per axis, the fused
+    // kernel's 8-plane tiles take 2.15 ms, the plain kernel's 24-plane tiles
+    // 2.31 ms
     if (dim == 3)
       plan_level3(d, fused || steps[0].mask_write >= 0, fused);
     else
@@ -330,7 +334,7 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     }
     if (launch_classify_quad(q, st) != hipSuccess) return PCRIT_E_HIP;
   } else if (launch_classify(a, dim, !fused && s0.mask_read >= 0,
-                             !fused && s0.mask_write >= 0, st) != hipSuccess) {
+                             !fused && s0.mask_write >= 0, fused, st) != hipSuccess) {
     return PCRIT_E_HIP;
   }
   record_kernel(c, 0, tlevel, 1, st);
@@ -1154,8 +1158,9 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
     off = c->boff;
   }
   if (st) return st;
-  // the first group's lists start at off[0] = 0
-  if (hipMemsetAsync(off, 0, sizeof(int64_t), s) != hipSuccess) return PCRIT_E_HIP;
+  // the first group's lists start at off[0] = 0 (a kernel, not a memset, so
+  // that the call can be captured in a graph)
+  if (launch_zero_i64(off, 1, s) != hipSuccess) return PCRIT_E_HIP;
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
   for (int i0 = 0; i0 < n_fields; i0 += kMaxFused) {

@@ -1147,9 +1147,9 @@ void plan_level2(LevelDesc &l, bool fused) {
 }
 
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
-                           bool write_masks, hipStream_t st) {
-  // fused launches compute the previous level's masks from the field
-  const bool fused = a.nl > 1;
+                           bool write_masks, bool fused, hipStream_t st) {
+  // fused launches (several levels, or a batch of fields) compute an old
+  // vertex's previous-level mask from the field when their level asks for it
   if (dim == 3) {
     // the kernel's LDS staging holds tiles of at most zchunk_cap3 planes
     for (int l = 0; l < a.nl; l++)

@@ -373,6 +373,11 @@ __global__ void fill_kernel(float *p, int n, float v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void zero_i64_kernel(int64_t *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 // Inputs of the coarse vertices of level `level` (stride s): vertex q
 // (level-local index) gets the 27 samples f(v + s d), d in {-1,0,1}^3
 // (clamped to the grid), as (f(v + s d) - f(v)) / max |f(v + s d) - f(v)|
@@ -654,6 +659,11 @@ hipError_t launch_region_tiles(const LevelDesc &l, int R, int s, int E, int nry,
 
 hipError_t launch_wait_stamp(uint64_t *out, double us, hipStream_t st) {
   hipLaunchKernelGGL(wait_stamp_kernel, dim3(1), dim3(64), 0, st, out, (uint64_t)(us * 100.0));
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_i64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -197,8 +197,10 @@ inline bool small_chunks(int64_t launch_words) { return launch_words <= kSmallLa
 hipError_t launch_publish_offsets(const int64_t *level_base, int n,
                                   const unsigned *nan_flag, unsigned gen,
                                   int64_t *out, hipStream_t st);
+// fused: several levels or fields in one launch (one tile per wave; old
+// vertices tested against masks computed from the field where asked)
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,
-                           bool write_masks, hipStream_t st);
+                           bool write_masks, bool fused, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, bool small, hipStream_t st);
 
 // Quad tiles: 256 level columns (four per lane, one 16-byte load per row for
@@ -316,6 +318,9 @@ hipError_t launch_region_tiles(const LevelDesc &l, int R, int s, int E, int nry,
                                int *scratch, hipStream_t st);
 // Stores the GPU clock (100 MHz) in *out.
 hipError_t launch_stamp(uint64_t *out, hipStream_t st);
+// Zeroes n int64 values with a kernel (a memset node misbehaves in captured
+// graphs).
+hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t st);
 // Waits about `us` microseconds on the GPU, then stores the clock in *out.
 hipError_t launch_wait_stamp(uint64_t *out, double us, hipStream_t st);
 

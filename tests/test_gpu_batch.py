@@ -102,3 +102,38 @@ def test_batch_rejects_mixed_dimensions(ctx, dev):
     with pytest.raises(pc.PcritError) as e:
         pc.classify_batch([a, b], ctx=ctx)
     assert e.value.status == pc.E_ARG
+
+
+def test_batch_in_captured_graph(ctx, dev):
+    """The batch call (device offsets) captured in a graph: replays with eager
+    work in between give the eager call's codes, lists and offsets each
+    time."""
+    fs = _fields(11, 20, 3, 12, 40)
+    ts = [torch.from_numpy(f).to(dev) for f in fs]
+    ref = pc.classify_batch(ts, ctx=ctx)
+    n = int(ref.offsets[-1])
+    total = sum(f.size for f in fs)
+    codes = [torch.zeros(t.shape, dtype=torch.uint8, device=dev) for t in ts]
+    crit = torch.empty(total, dtype=torch.int32, device=dev)
+    offs = torch.empty(len(ts) + 1, dtype=torch.int64, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up: scratch grown before capture
+        pc.classify_batch(ts, ctx=ctx, codes=codes, crit=crit, offsets_dev=offs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pc.classify_batch(ts, ctx=ctx, codes=codes, crit=crit, offsets_dev=offs)
+    for rep in range(3):
+        for c in codes:
+            c.zero_()
+        crit.fill_(-1)
+        offs.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(offs.cpu().numpy(), ref.offsets), rep
+        assert torch.equal(crit[:n], ref.crit[:n]), rep
+        for c, r in zip(codes, ref.codes):
+            assert torch.equal(c, r), rep
