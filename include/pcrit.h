@@ -414,6 +414,30 @@ int pcrit_classify_batch(pcrit_ctx *ctx, void *hip_stream, int n_fields,
                          uint8_t *crit_codes, int64_t crit_capacity,
                          int64_t *offsets_host, int64_t *offsets_dev);
 
+/* ------------------------------------------------------------------------
+ * Order field and extremum lists (the scope table's third "next" row: the
+ * inputs of the paper's simplification).
+ * ---------------------------------------------------------------------- */
+
+/* The order field of Section 4.1: every vertex ranked by (value, memory
+ * index), ties by index, -0 == +0:
+ *   rank[i] = #{ j : f[j] < f[i] or (f[j] == f[i] and j < i) },
+ *   sorted[r] = the vertex of rank r
+ * (device, N uint32 each, caller-owned).  A radix sort on the GPU; the call
+ * waits for the stream.  PCRIT_E_NAN if a sample is NaN (outputs then
+ * unspecified).  Dims as for pcrit_classify (N <= 2^32 - 1). */
+int pcrit_order_field(pcrit_ctx *ctx, void *hip_stream, const float *field, int64_t nx,
+                      int64_t ny, int64_t nz, uint32_t *rank, uint32_t *sorted);
+
+/* The extremum lists of full-resolution codes (as written by
+ * pcrit_classify at level 0): minima (empty lower link, code & 7 == 0), then
+ * maxima (empty upper link, code & 0x38 == 0), each ascending, into out
+ * (device, capacity entries; entries past it are not written).
+ * counts_host[0] = minima, counts_host[1] = maxima; PCRIT_E_CAPACITY if
+ * their sum exceeds the capacity.  The call waits for the stream. */
+int pcrit_extrema(pcrit_ctx *ctx, void *hip_stream, const uint8_t *codes, int64_t nx,
+                  int64_t ny, int64_t nz, uint32_t *out, int64_t capacity, int64_t *counts_host);
+
 #ifdef __cplusplus
 }
 #endif

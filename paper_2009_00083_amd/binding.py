@@ -32,7 +32,7 @@ EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_preview_f1_levels", "pcrit_mlp_feature_level", "pcrit_mlp_features",
             "pcrit_mlp_labels", "pcrit_mlp_forward", "pcrit_mlp_backward",
             "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline",
-            "pcrit_classify_batch")
+            "pcrit_classify_batch", "pcrit_order_field", "pcrit_extrema")
 MLP_PARAMS = 6337
 MLP_INPUTS = 32
 
@@ -77,6 +77,10 @@ def _load():
     lib.pcrit_classify_noalloc.restype = i32
     lib.pcrit_classify_batch.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp]
     lib.pcrit_classify_batch.restype = i32
+    lib.pcrit_order_field.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp]
+    lib.pcrit_order_field.restype = i32
+    lib.pcrit_extrema.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
+    lib.pcrit_extrema.restype = i32
     lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
     lib.NULL_CB = ctypes.cast(None, lib.LEVEL_CB)
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
@@ -395,6 +399,43 @@ def classify_batch(fields, *, ctx: Optional[Context] = None, capacity: Optional[
     if check and st not in (0, E_CAPACITY):
         raise PcritError(st, "pcrit_classify_batch")
     return BatchResult(out_codes, crit, cc, offs, st)
+
+
+def order_field(field, *, ctx: Optional[Context] = None, rank=None, sorted_out=None,
+                stream=None):
+    """(rank, sorted): the order field of ``field`` -- every vertex's rank by
+    (value, index) -- and the vertex at each rank (int32 tensors holding
+    uint32 values, flat)."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    c = _ctx_for(field, ctx)
+    n = field.numel()
+    if rank is None:
+        rank = torch.empty(n, dtype=torch.int32, device=field.device)
+    if sorted_out is None:
+        sorted_out = torch.empty(n, dtype=torch.int32, device=field.device)
+    check_buffer("rank", rank, torch.int32, field.device, numel=n)
+    check_buffer("sorted_out", sorted_out, torch.int32, field.device, numel=n)
+    _check(_load().pcrit_order_field(c.handle, _stream_handle(field, stream), _ptr(field), nx, ny,
+                                     nz, _ptr(rank), _ptr(sorted_out)), "pcrit_order_field")
+    return rank, sorted_out
+
+
+def extrema(codes, *, ctx: Optional[Context] = None, capacity: Optional[int] = None,
+            stream=None):
+    """(minima, maxima) of full-resolution codes: ascending int32 tensors."""
+    import torch
+    if codes.dtype != torch.uint8 or not codes.is_contiguous():
+        raise PcritError(E_ARG, "codes must be contiguous uint8")
+    nx, ny, nz = _shape3(codes.shape)
+    c = _ctx_for(codes, ctx)
+    cap = codes.numel() * 2 if capacity is None else int(capacity)
+    out = torch.empty(max(cap, 1), dtype=torch.int32, device=codes.device)
+    cnt = np.zeros(2, np.int64)
+    _check(_load().pcrit_extrema(c.handle, _stream_handle(codes, stream), _ptr(codes), nx, ny, nz,
+                                 _ptr(out), cap, cnt.ctypes.data), "pcrit_extrema")
+    a, b = int(cnt[0]), int(cnt[1])
+    return out[:a], out[a:a + b]
 
 
 def classify_noalloc(field, level: int, codes, crit, *, ctx: Context,

@@ -116,6 +116,8 @@ struct pcrit_ctx {
   int64_t tl_bytes = 0;
   int64_t *boff = nullptr;  // list offsets of a batch (when the caller gives none)
   int64_t boff_bytes = 0;
+  void *ord = nullptr;  // order-field sort scratch
+  int64_t ord_bytes = 0;
   // second stream (default priority) on which the learned order is scored
   // while the leading levels run, and the events that fork and join it
   hipStream_t side = nullptr;
@@ -479,6 +481,7 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->reclass_acc);
   hipFree(c->tl);
   hipFree(c->boff);
+  hipFree(c->ord);
   hipFree(c->status);
   if (c->side) hipStreamDestroy(c->side);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
@@ -1177,5 +1180,80 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
     return PCRIT_E_HIP;
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
   return offsets_host[n_fields] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
+}
+
+// ------------------------------------------------------------------------
+// Order field and extremum lists.
+int pcrit_order_field(pcrit_ctx *c, void *hip_stream, const float *field, int64_t nx,
+                      int64_t ny, int64_t nz, uint32_t *rank, uint32_t *sorted) {
+  if (!c || !field || !rank || !sorted || misaligned(field, 4) || misaligned(rank, 4) ||
+      misaligned(sorted, 4))
+    return PCRIT_E_ARG;
+  int st = check_dims(nx, ny, nz);
+  if (st) return st;
+  const int64_t n = nx * ny * nz;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  hipStream_t s = (hipStream_t)hip_stream;
+  st = ensure(&c->ord, &c->ord_bytes, order_scratch_bytes(n));
+  if (st) return st;
+  const unsigned gen = next_gen(c);
+  if (launch_order_field(field, n, rank, sorted, c->ord, &c->flags[0], gen, s) != hipSuccess ||
+      read_status(c, s))
+    return PCRIT_E_HIP;
+  return c->h_flags[0] == gen ? PCRIT_E_NAN : PCRIT_OK;
+}
+
+int pcrit_extrema(pcrit_ctx *c, void *hip_stream, const uint8_t *codes, int64_t nx, int64_t ny,
+                  int64_t nz, uint32_t *out, int64_t capacity, int64_t *counts_host) {
+  if (!c || !codes || capacity < 0 || (capacity > 0 && !out) || !counts_host ||
+      (out && misaligned(out, 4)))
+    return PCRIT_E_ARG;
+  int st = check_dims(nx, ny, nz);
+  if (st) return st;
+  const int64_t rows = ny * nz, rowwords = (nx + 63) / 64, words = rows * rowwords;
+  const bool small = small_chunks(2 * words);
+  const int64_t cw = small ? kSmallChunkWords : kChunkWords;
+  const int64_t chunks_per = (words + cw - 1) / cw;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  hipStream_t s = (hipStream_t)hip_stream;
+  st = ensure((void **)&c->bits, &c->bits_words, 2 * words * 8);
+  if (!st) st = ensure((void **)&c->counts, &c->counts_n, 2 * chunks_per * (int64_t)sizeof(int));
+  if (!st) st = ensure((void **)&c->boff, &c->boff_bytes, 8 * 3);
+  if (st) return st;
+  CompactArgs b{};
+  b.nl = 2;
+  b.nchunks = (int)(2 * chunks_per);
+  for (int l = 0; l < 2; l++) {
+    CompactLevel &q = b.lv[l];
+    q.codes = codes;
+    q.nx = nx;
+    q.ny = ny;
+    q.bits = c->bits + l * words;
+    q.words = words;
+    q.rowwords = (int)rowwords;
+    q.mx = (int)nx;
+    q.my = (int)ny;
+    q.s = 1;
+    q.slot = l;
+    q.chunk_begin = (int)(l * chunks_per);
+    q.linear = nx == rowwords * 64;
+  }
+  b.crit = out;
+  b.cap = capacity;
+  b.level_base = c->boff;
+  b.nan_flag = &c->flags[0];
+  b.gen = next_gen(c);
+  b.counts = c->counts;
+  b.reclass_acc = c->reclass_acc;
+  int64_t off[3];
+  if (launch_zero_i64(c->boff, 1, s) != hipSuccess ||
+      launch_extrema_bits(codes, nx, rows, (int)rowwords, c->bits, s) != hipSuccess ||
+      launch_compact(b, small, s) != hipSuccess ||
+      hipMemcpyAsync(off, c->boff, sizeof(off), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return PCRIT_E_HIP;
+  counts_host[0] = off[1] - off[0];
+  counts_host[1] = off[2] - off[1];
+  return off[2] > capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
 }  // extern "C"

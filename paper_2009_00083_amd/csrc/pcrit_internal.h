@@ -321,6 +321,17 @@ hipError_t launch_stamp(uint64_t *out, hipStream_t st);
 // Zeroes n int64 values with a kernel (a memset node misbehaves in captured
 // graphs).
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t st);
+
+// Order field (order.hip): rank[i] of every sample by (value, index) and the
+// sample at each rank (sorted, also the sort's value buffer); scratch of
+// order_scratch_bytes(n) bytes; a NaN sample sets *nan_flag = gen.
+int64_t order_scratch_bytes(int64_t n);
+hipError_t launch_order_field(const float *f, int64_t n, uint32_t *rank, uint32_t *sorted,
+                              void *scratch, unsigned *nan_flag, unsigned gen, hipStream_t st);
+// Minimum and maximum bits of full-resolution codes: rows * rowwords words
+// of minima, then as many of maxima.
+hipError_t launch_extrema_bits(const uint8_t *codes, int64_t nx, int64_t rows, int rowwords,
+                               uint64_t *bits, hipStream_t st);
 // Waits about `us` microseconds on the GPU, then stores the clock in *out.
 hipError_t launch_wait_stamp(uint64_t *out, double us, hipStream_t st);
 
