@@ -17,8 +17,9 @@ plain level order, for region-by-region refinement in region id order and
 in the learned order (the order network trained, untimed, on held-out
 fields), on this field and on the smooth recipe at 512^3; "batch": 200
 independent fields of 33..257 samples per axis classified with shared
-launches against one call per field; the direct level-0 rate; per-level
-rates; the roofline of the dominant kernel; and the CPU
+launches against one call per field; "order_field": the order field
+(ranks by value, ties by index) and extremum lists of the bench field; the
+direct level-0 rate; per-level rates; the roofline of the dominant kernel; and the CPU
 oracle's rate on bounded samples of the same workload (all threads of this
 process's share, and one thread).
 """
@@ -184,6 +185,35 @@ def batch_measure(pc, ctx, dev, reps=10):
                 "critical": int(ref.offsets[-1]),
                 "speedup": round(out["per_field_ms"] / out["batched_ms"], 2)})
     return out
+
+
+def order_measure(pc, ctx, ft, codes, reps=5):
+    """Order field (ranks by value, ties by index) and extremum lists of the
+    bench field; algorithmic bytes of the order field: the field read and
+    the ranks written, 8 B per vertex."""
+    import torch
+    n = ft.numel()
+    rank = torch.empty(n, dtype=torch.int32, device=ft.device)
+    srt = torch.empty(n, dtype=torch.int32, device=ft.device)
+    pc.order_field(ft, ctx=ctx, rank=rank, sorted_out=srt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pc.order_field(ft, ctx=ctx, rank=rank, sorted_out=srt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    pc.extrema(codes, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mn, mx = pc.extrema(codes, ctx=ctx)
+    torch.cuda.synchronize()
+    ems = (time.perf_counter() - t0) * 1e3 / reps
+    gbs = 8 * n / (ms * 1e-3) / 1e9
+    return {"order_field_ms": round(ms, 3), "order_field_gkeys": round(n / (ms * 1e-3) / 1e9, 2),
+            "order_field_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "extrema_ms": round(ems, 3), "minima": int(mn.numel()), "maxima": int(mx.numel()),
+            "note": "both calls wait for the stream; times include the host wait"}
 
 
 def _region_of(points, shape, edge):
@@ -489,6 +519,7 @@ def main():
 
     if not args.no_batch:
         out["batch"] = batch_measure(pc, ctx, dev)
+        out["order_field"] = order_measure(pc, ctx, ft, codes)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -7,9 +7,9 @@
 // the vertex indices as values: a stable sort of keys that start in index
 // order leaves equal keys in index order, which is exactly the tie-break.
 // Four passes of 8 bits, each three kernels: per-tile digit histograms, one
-// exclusive scan over (digit, tile), and a stable scatter that ranks each
-// key among the equal digits of its tile (wave ballots on the digit's bits,
-// per-wave digit counts in LDS) and writes it at its digit's offset.
+// exclusive scan over (digit, tile), and a stable scatter that sorts each
+// tile by digit in LDS (wave ballots on the digit's bits, per-wave digit
+// counts) and writes its digit runs at their offsets.
 // Finally rank[sorted[i]] = i.
 //
 // The extremum lists (the minima and maxima the paper's simplification
@@ -145,26 +145,48 @@ __global__ __launch_bounds__(kSortThreads) void scan_chunks_kernel(uint32_t *a, 
 
 // Stable scatter of tile t: key i of the tile goes to
 // offset[d * ntiles + t] + (keys of digit d before it in the tile).  The
-// tile is taken in rounds of kSortThreads keys (thread order = index
-// order); within a wave, the lanes with the same digit are found by ballots
-// on its 8 bits; across the waves of a round and across rounds, counts per
-// digit in LDS.
+// tile's keys are first placed in LDS in digit order (a stable local sort:
+// the tile is taken in rounds of kSortThreads keys, thread order = index
+// order; within a wave the lanes with the same digit are found by ballots
+// on its 8 bits, across waves and rounds by counts per digit in LDS), then
+// written out in that order, so that consecutive threads write consecutive
+// positions of a digit's run.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *keys, const uint32_t *vals, uint32_t n, int shift, uint32_t ntiles,
     const uint32_t *offset, uint32_t *keys_out, uint32_t *vals_out) {
-  __shared__ uint32_t s_base[kRadix];             // this tile's next slot per digit
+  __shared__ uint32_t s_key[kSortTile], s_val[kSortTile];
+  __shared__ uint32_t s_lpre[kRadix];              // tile-local start of each digit
+  __shared__ uint32_t s_run[kRadix];               // keys of each digit placed so far
+  __shared__ uint32_t s_gbase[kRadix];             // global start of each digit
   __shared__ uint32_t s_wcnt[kSortWaves][kRadix];  // keys per wave and digit in a round
+  __shared__ uint32_t s_w[kSortWaves];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  s_base[tid] = offset[(uint64_t)tid * ntiles + blockIdx.x];
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const uint32_t cnt = (uint32_t)min((uint64_t)kSortTile, (uint64_t)n - base);
+  uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++) {
+    const uint32_t j = (uint32_t)k * kSortThreads + tid;
+    key[k] = j < cnt ? keys[base + j] : 0u;
+    val[k] = j < cnt ? vals[base + j] : 0u;
+  }
+  s_run[tid] = 0u;
+  s_gbase[tid] = offset[(uint64_t)tid * ntiles + blockIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++)
+    if ((uint32_t)k * kSortThreads + tid < cnt) atomicAdd(&s_run[(key[k] >> shift) & 0xFFu], 1u);
+  __syncthreads();
+  uint32_t total;
+  s_lpre[tid] = block_exclusive_scan(s_run[tid], s_w, &total);
+  s_run[tid] = 0u;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes below this one
+#pragma unroll
   for (int k = 0; k < kSortItems; k++) {
     for (int i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0u;
     __syncthreads();
-    const uint64_t i = base + (uint64_t)k * kSortThreads + tid;
-    const bool ok = i < n;
-    const uint32_t key = ok ? keys[i] : 0u, val = ok ? vals[i] : 0u;
-    const uint32_t d = (key >> shift) & 0xFFu;
+    const bool ok = (uint32_t)k * kSortThreads + tid < cnt;
+    const uint32_t d = (key[k] >> shift) & 0xFFu;
     uint64_t peers = wave_ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -176,17 +198,23 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     if (ok && (peers & lt) == 0ull) s_wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (ok) {
-      uint32_t before = s_base[d];
-      for (int v = 0; v < w; v++) before += s_wcnt[v][d];
-      keys_out[before + wrank] = key;
-      vals_out[before + wrank] = val;
+      uint32_t pos = s_lpre[d] + s_run[d] + wrank;
+      for (int v = 0; v < w; v++) pos += s_wcnt[v][d];
+      s_key[pos] = key[k];
+      s_val[pos] = val[k];
     }
     __syncthreads();
     uint32_t sum = 0;
 #pragma unroll
     for (int v = 0; v < kSortWaves; v++) sum += s_wcnt[v][tid];
-    s_base[tid] += sum;
-    __syncthreads();
+    s_run[tid] += sum;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < cnt; j += kSortThreads) {
+    const uint32_t kk = s_key[j], d = (kk >> shift) & 0xFFu;
+    const uint32_t g = s_gbase[d] + (j - s_lpre[d]);
+    keys_out[g] = kk;
+    vals_out[g] = s_val[j];
   }
 }
 
