@@ -95,6 +95,10 @@ struct QPlane {
                     // 16+i column x0, lane 48+i column x0+256
 };
 
+// s_waitcnt operand: vmcnt 0, expcnt and lgkmcnt unconstrained (GFX9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVmem = 0x0F70;
+
 // GEN: the tile has rows or planes on the y or z boundary of the level.
 template <int R, int SX, bool GEN>
 __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
@@ -282,10 +286,18 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
     });
   }
 
-  // Bitmask words: lane 16 k + 15 ends with word 4 tx + k of the row.
+  // Bitmask words: lane 16 k + 15 ends with word 4 tx + k of each row; one
+  // store per step writes the R rows' words, row j from lane 16 k + 15 - j.
+  // Every lane takes part in it: the other lanes' offsets lie past the
+  // record limit, so the hardware drops their writes, and the store needs no
+  // branch (a branch around a store makes the compiler wait for the stores
+  // of one step before the next step's loads may be used).
   const int wshift = 4 * (lane & 7);
-  const bool wlane = (lane & 15) == 15 && 4 * tp.tx + (lane >> 4) < g.rowwords;
-  uint64_t *const wbase = g.bits + 4 * tp.tx + (lane >> 4);
+  const uint32_t wrec = (uint32_t)g.rowwords * 8u;  // bytes of a row of words
+  const int wrow = 15 - (lane & 15);
+  const uint32_t wvo = wrow < R && 4 * tp.tx + (lane >> 4) < g.rowwords
+                           ? (uint32_t)(4 * tp.tx + (lane >> 4)) * 8u + (uint32_t)wrow * wrec
+                           : 0x80000000u;
   const unsigned vnib = (1u << nval) - 1u;  // valid columns of this lane
   const uint32_t sy = (uint32_t)g.sy;
   uint8_t *const codes = a.codes;
@@ -311,6 +323,7 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
     });
     const unsigned az = GEN ? (z == 0 ? QAZM : 0u) | (z == mz - 1 ? QAZP : 0u) : 0u;
     const __amdgpu_buffer_rsrc_t crs = rsrc_n(codes + (int64_t)z * g.sz, crec);
+    uint32_t wq[R][2];  // each row's bitmask word (low, high half)
     static_for<R>([&](auto ic) {
       constexpr int i = decltype(ic)::value + 1;
       const int y = y0 + i - 1;
@@ -356,15 +369,19 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
           cr[e] = edge ? (code[e] & 0xBFu) != 0x09u : code[e] != 0x09u;
         });
       }
-      if (!GEN || y < my) {
+      {
+        // a row past the level (odd my) stores nothing: its offsets lie
+        // past the record limit, with no branch around the store
+        const bool rv = !GEN || y < my;
         if (SX == 1) {
           const unsigned packed = code[0] | (code[1] << 8) | (code[2] << 16) | (code[3] << 24);
-          __builtin_amdgcn_raw_buffer_store_b32(packed, crs, cvo[0], (uint32_t)y * sy, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(packed, crs, rv ? cvo[0] : 0x80000000u,
+                                                (uint32_t)y * sy, 0);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; e++)
-            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)code[e], crs, cvo[e],
-                                                 (uint32_t)y * sy, 0);
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)code[e], crs,
+                                                 rv ? cvo[e] : 0x80000000u, (uint32_t)y * sy, 0);
         }
         // this lane's four bits, moved to their place in its half of the
         // word of its sixteen-lane row; three DPP ORs gather lanes 0..7 of
@@ -380,11 +397,30 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
           wv |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wv, 0x110 + d, 0xF, 0xF, true);
         });
         const uint32_t wlo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wv, 0x118, 0xF, 0xF, true);
-        if (wlane) wbase[((int64_t)z * my + y) * g.rowwords] = ((uint64_t)wv << 32) | wlo;
+        wq[i - 1][0] = wlo;
+        wq[i - 1][1] = wv;
       }
     });
+    // row j's word moves from lane 16 k + 15 to lane 16 k + 15 - j; rows
+    // past the level lie past the record limit
+    uint32_t dlo = wq[0][0], dhi = wq[0][1];
+    static_for<R - 1>([&](auto jc) {
+      constexpr int j = decltype(jc)::value + 1;
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wq[j][0], 0x100 + j, 0xF, 0xF, true);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wq[j][1], 0x100 + j, 0xF, 0xF, true);
+      dlo = wrow == j ? lo : dlo;
+      dhi = wrow == j ? hi : dhi;
+    });
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 wd = {dlo, dhi};
+    const uint32_t nrow = GEN ? (uint32_t)min(R, my - y0) : (uint32_t)R;
+    __builtin_amdgcn_raw_buffer_store_b64(
+        wd, rsrc_n(g.bits + ((int64_t)z * my + y0) * g.rowwords, nrow * wrec), wvo, 0, 0);
   };
 
+  // the prologue's loads have landed: each step's wait then counts only the
+  // previous step's loads and lets its stores run on
+  __builtin_amdgcn_s_waitcnt(kWaitVmem);
   for (int zb = z0; zb < z1; zb += U) {
     static_for<U>([&](auto uc) {
       const int z = zb + decltype(uc)::value;
@@ -444,15 +480,11 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
   }
 }
 
-// s_waitcnt operand: vmcnt 0, expcnt and lgkmcnt unconstrained (GFX9
-// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
-constexpr int kWaitVmem = 0x0F70;
-
 // LISTED: tiles from the region-ordered per-XCD lists (QuadArgs::tile_list)
 // instead of a grid-stride walk over the level.
 template <int R, int SX, bool LISTED>
 __global__ __launch_bounds__(64 * kQuadBlockWaves)
-__attribute__((amdgpu_waves_per_eu(SX == 1 ? kQuadWavesPerSimd : kQuadWavesPerSimd - 1)))
+__attribute__((amdgpu_waves_per_eu(kQuadWavesPerSimd)))
 void classify3d_quad_kernel(QuadArgs a) {
   constexpr int NW = kQuadBlockWaves;
   __shared__ __attribute__((aligned(16))) uint8_t slut[kQuadTableBytes];

@@ -220,9 +220,12 @@ constexpr int kQuadRows = PCRIT_QUAD_ROWS;
 constexpr int kQuadSlots = PCRIT_QUAD_SLOTS;  // planes held in registers per wave
 constexpr int kQuadZChunk = PCRIT_QUAD_ZCHUNK;
 #ifndef PCRIT_QUAD_WAVES
-#define PCRIT_QUAD_WAVES 4
+#define PCRIT_QUAD_WAVES 3
 #endif
-constexpr int kQuadWavesPerSimd = PCRIT_QUAD_WAVES;  // occupancy the kernel is built for
+// the fewest waves per SIMD the quad kernel is built for: it sets the
+// register budget (512 / waves); the full-resolution kernel stays within 128
+// registers (four waves) and is scheduled better with the wider budget
+constexpr int kQuadWavesPerSimd = PCRIT_QUAD_WAVES;
 #ifndef PCRIT_QUAD_BLOCK_WAVES
 #define PCRIT_QUAD_BLOCK_WAVES 4
 #endif
