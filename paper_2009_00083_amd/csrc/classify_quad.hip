@@ -88,11 +88,29 @@ __device__ __forceinline__ unsigned quad_boundary(const uint8_t *lut, unsigned i
   return (eL & 7u) | (eU & 0x38u) | 0x40u | (holes << 7);
 }
 
-template <int R>
+template <int R, int SX>
 struct QPlane {
-  float4 v[R + 2];  // rows y0-1 .. y0+R: level columns c0 .. c0+3 of this lane
+  // SX = 1: rows y0-1 .. y0+R, level columns c0 .. c0+3 of this lane.  SX =
+  // 2: each row's eight samples as loaded (the level columns are the even
+  // ones), kept as loaded so that no copy waits for the load
+  float4 raw[SX][R + 2];
   float h;          // packed halo: lane i < R+2 column x0-1 of row i, lane
                     // 16+i column x0, lane 48+i column x0+256
+  __device__ __forceinline__ float4 v(int i) const {
+    if constexpr (SX == 1)
+      return raw[0][i];
+    else
+      return make_float4(raw[0][i].x, raw[0][i].z, raw[1][i].x, raw[1][i].z);
+  }
+  // SX = 2: the odd samples are never read, so the compiler would hand their
+  // registers to other values while the load is in flight and wait for it
+  // there; an empty use just before the slot is loaded again keeps them
+  __device__ __forceinline__ void keep() const {
+    if constexpr (SX == 2) {
+#pragma unroll
+      for (int i = 0; i < R + 2; i++) asm volatile("" ::"v"(raw[0][i].y), "v"(raw[1][i].y));
+    }
+  }
 };
 
 // s_waitcnt operand: vmcnt 0, expcnt and lgkmcnt unconstrained (GFX9
@@ -100,7 +118,10 @@ struct QPlane {
 constexpr int kWaitVmem = 0x0F70;
 
 // GEN: the tile has rows or planes on the y or z boundary of the level.
-template <int R, int SX, bool GEN>
+// CODES: the codes are stored (always at stride 1; at stride 2 a launch
+// without a codes array, as in progressive calls without list codes, leaves
+// the store instructions out).
+template <int R, int SX, bool GEN, bool CODES>
 __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
                                           const uint8_t *slut, bool &nan_seen) {
   const LevelDesc &g = a.lv;
@@ -149,31 +170,27 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
     const int64_t rem = a.fbytes - pz;
     return rsrc_n(fb + pz, rem > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)rem);
   };
-  auto load = [&](int z, QPlane<R> &d) {
+  auto load = [&](int z, QPlane<R, SX> &d) {
     const __amdgpu_buffer_rsrc_t r = plane_rsrc(z);
 #pragma unroll
     for (int i = 0; i < NR; i++) {
-      if (SX == 1) {
-        d.v[i] = ld128(r, xoff, roff[i]);
-      } else {
-        const float4 p = ld128(r, xoff, roff[i]), q = ld128(r, xoff + 16, roff[i]);
-        d.v[i] = make_float4(p.x, p.z, q.x, q.z);
-      }
+      d.raw[0][i] = ld128(r, xoff, roff[i]);
+      if (SX == 2) d.raw[SX - 1][i] = ld128(r, xoff + 16, roff[i]);
     }
     d.h = ld_f32(r, hoff);
   };
   // x+1 neighbour of each row's last column: the next lane's first column,
   // at lane 63 the right halo
-  auto derive_s = [&](const QPlane<R> &d, float *s) {
+  auto derive_s = [&](const QPlane<R, SX> &d, float *s) {
     static_for<NR - 1>([&](auto ic) {
       constexpr int i = decltype(ic)::value + 1;  // row 0 needs none
       const float go = mov_dpp_f<0x110 + (15 - i)>(d.h);  // row_shr: lane 63 <- lane 48+i
-      s[i] = dpp_f<kDppShl1>(go, d.v[i].x);
+      s[i] = dpp_f<kDppShl1>(go, d.v(i).x);
     });
   };
   // column x0 of every row, lane i <- lane 16+i (rows 0 and 1 of the
   // wave swapped)
-  auto derive_a = [&](const QPlane<R> &d) {
+  auto derive_a = [&](const QPlane<R, SX> &d) {
     const unsigned hb = __float_as_uint(d.h);
     return __uint_as_float(__builtin_amdgcn_permlane16_swap(hb, hb, false, false)[1]);
   };
@@ -255,7 +272,7 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
   }
   const uint32_t crec = a.codes ? (uint32_t)g.sz : 0u;  // bytes of a plane of codes
 
-  QPlane<R> F[NS];
+  QPlane<R, SX> F[NS];
   float S[NS][NR];
   float AV[NS];
   unsigned PB[2][R + 1], PSB[2][R + 1];
@@ -274,11 +291,11 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
   AV[1] = derive_a(F[1]);
   {
     const unsigned hp = halo_p(F[0].h, AV[0], AV[1]);
-    PB[0][0] = prow0(F[0].v[0], F[0].v[1], S[0][1], F[1].v[1], S[1][1]);
+    PB[0][0] = prow0(F[0].v(0), F[0].v(1), S[0][1], F[1].v(1), S[1][1]);
     static_for<R>([&](auto ic) {
       constexpr int i = decltype(ic)::value + 1;
-      PB[0][i] = prow(F[0].v[i], S[0][i], F[0].v[i + 1], S[0][i + 1], F[1].v[i], S[1][i],
-                      F[1].v[i + 1], S[1][i + 1]);
+      PB[0][i] = prow(F[0].v(i), S[0][i], F[0].v(i + 1), S[0][i + 1], F[1].v(i), S[1][i],
+                      F[1].v(i + 1), S[1][i + 1]);
     });
     static_for<R + 1>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -307,15 +324,16 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
     // slots of planes z, z+1 and z+NS-1 (the slot plane z-1 frees)
     constexpr int s0 = (u + 1) % NS, s1 = (u + 2) % NS, s2 = u % NS;
     constexpr int pc = (u + 1) % 2, pp = u % 2;                    // P of planes z, z-1
+    F[s2].keep();
     load(min(z + NS - 1, zlim), F[s2]);
     derive_s(F[s1], S[s1]);
     AV[s1] = derive_a(F[s1]);
     const unsigned hp = halo_p(F[s0].h, AV[s0], AV[s1]);
-    PB[pc][0] = prow0(F[s0].v[0], F[s0].v[1], S[s0][1], F[s1].v[1], S[s1][1]);
+    PB[pc][0] = prow0(F[s0].v(0), F[s0].v(1), S[s0][1], F[s1].v(1), S[s1][1]);
     static_for<R>([&](auto ic) {
       constexpr int i = decltype(ic)::value + 1;
-      PB[pc][i] = prow(F[s0].v[i], S[s0][i], F[s0].v[i + 1], S[s0][i + 1], F[s1].v[i],
-                       S[s1][i], F[s1].v[i + 1], S[s1][i + 1]);
+      PB[pc][i] = prow(F[s0].v(i), S[s0][i], F[s0].v(i + 1), S[s0][i + 1], F[s1].v(i),
+                       S[s1][i], F[s1].v(i + 1), S[s1][i + 1]);
     });
     static_for<R + 1>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -338,7 +356,7 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
         idx[e] = __builtin_amdgcn_perm(N, P, 0x0C0C0000u | ((4u + e) << 8) | e);
         code[e] = slut[idx[e]];
       });
-      const float4 C = F[s0].v[i];
+      const float4 C = F[s0].v(i);
       special |= wave_ballot(special_centre(C.x) | special_centre(C.y) |
                              special_centre(C.z) | special_centre(C.w));
       bool cr[4];  // critical
@@ -377,7 +395,7 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
           const unsigned packed = code[0] | (code[1] << 8) | (code[2] << 16) | (code[3] << 24);
           __builtin_amdgcn_raw_buffer_store_b32(packed, crs, rv ? cvo[0] : 0x80000000u,
                                                 (uint32_t)y * sy, 0);
-        } else {
+        } else if (CODES) {
 #pragma unroll
           for (int e = 0; e < 4; e++)
             __builtin_amdgcn_raw_buffer_store_b8((unsigned char)code[e], crs,
@@ -482,7 +500,7 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, int t, int lane,
 
 // LISTED: tiles from the region-ordered per-XCD lists (QuadArgs::tile_list)
 // instead of a grid-stride walk over the level.
-template <int R, int SX, bool LISTED>
+template <int R, int SX, bool LISTED, bool CODES>
 __global__ __launch_bounds__(64 * kQuadBlockWaves)
 __attribute__((amdgpu_waves_per_eu(kQuadWavesPerSimd)))
 void classify3d_quad_kernel(QuadArgs a) {
@@ -521,9 +539,9 @@ void classify3d_quad_kernel(QuadArgs a) {
     const bool inner = y0 >= 1 && y0 + R <= a.lv.my - 1 && z0 >= 1 &&
                        z0 + a.lv.zchunk <= a.lv.mz - 1;
     if (inner)
-      quad_tile<R, SX, false>(a, t, lane, slut, nan_seen);
+      quad_tile<R, SX, false, CODES>(a, t, lane, slut, nan_seen);
     else
-      quad_tile<R, SX, true>(a, t, lane, slut, nan_seen);
+      quad_tile<R, SX, true, CODES>(a, t, lane, slut, nan_seen);
     if (LISTED) {
       // the region's last tile stamps the clock once this tile's stores
       // have completed (a wait on the vector memory counter only: a
@@ -584,15 +602,20 @@ hipError_t launch_classify_quad(const QuadArgs &a, hipStream_t st) {
   if (a.tile_list) g = std::min((g + kXcds - 1) / kXcds * kXcds, 2048);
   const dim3 grid((unsigned)(g > 0 ? g : 1)), block(64 * kQuadBlockWaves);
   if (a.lv.sx != 1 && a.lv.sx != 2) return hipErrorInvalidValue;
+  const bool codes = a.codes != nullptr;
   if (a.tile_list) {
     if (a.lv.sx == 1)
-      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1, true>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1, true, true>), grid, block, 0, st, a);
+    else if (codes)
+      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, true, true>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, true>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, true, false>), grid, block, 0, st, a);
   } else if (a.lv.sx == 1) {
-    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 1, false, true>), grid, block, 0, st, a);
+  } else if (codes) {
+    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, false, true>), grid, block, 0, st, a);
   } else {
-    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((classify3d_quad_kernel<kQuadRows, 2, false, false>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
