@@ -87,6 +87,12 @@ struct pcrit_ctx {
   uint8_t *lutq = nullptr;  // quad-tile tables (kQuadTableBytes bytes)
   uint64_t *bits = nullptr;  // critical bitmasks of the levels of one launch
   int64_t bits_words = 0;
+  // the finest level's bitmask and chunk counts when it runs beside the
+  // coarser levels (progressive calls, see enqueue_progressive)
+  uint64_t *bits2 = nullptr;
+  int64_t bits2_words = 0;
+  int *counts2 = nullptr;
+  int64_t counts2_n = 0;
   int *counts = nullptr;  // per-chunk critical counts of the compaction
   int64_t counts_n = 0;
   uint8_t *lcodes = nullptr;  // dense codes of fused levels (for crit_codes)
@@ -152,6 +158,17 @@ int ensure(void **p, int64_t *have, int64_t bytes) {
   *have = 0;
   if (hipMalloc(p, (size_t)bytes) != hipSuccess) return PCRIT_E_OOM;
   *have = bytes;
+  return PCRIT_OK;
+}
+
+// The context's second stream (default priority) and the events that fork
+// work onto it and join it back.
+int ensure_side(pcrit_ctx *c) {
+  if (c->side) return PCRIT_OK;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+    return PCRIT_E_HIP;
   return PCRIT_OK;
 }
 
@@ -226,7 +243,8 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   uint8_t *crit_codes, int64_t cap, int64_t *count_dev,
                   unsigned gen, bool final_group, uint64_t *bits, int *counts,
                   int64_t *publish = nullptr, int publish_n = 0,
-                  const RegionHooks *rh = nullptr, int64_t *lbase = nullptr) {
+                  const RegionHooks *rh = nullptr, int64_t *lbase = nullptr,
+                  hipEvent_t compact_after = nullptr) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -353,6 +371,9 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   b.gen = gen;
   b.counts = counts;
   b.reclass_acc = c->reclass_acc;
+  // the lists of earlier launches that ran on another stream come first
+  if (compact_after && hipStreamWaitEvent(st, compact_after, 0) != hipSuccess)
+    return PCRIT_E_HIP;
   record_kernel(c, 1, tlevel, 0, st);
   if (launch_compact(b, small, st) != hipSuccess) return PCRIT_E_HIP;
   record_kernel(c, 1, tlevel, 1, st);
@@ -475,6 +496,8 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->lutq);
   hipFree(c->bits);
   hipFree(c->counts);
+  hipFree(c->bits2);
+  hipFree(c->counts2);
   hipFree(c->lcodes);
   hipFree(c->masks[0]);
   hipFree(c->masks[1]);
@@ -653,9 +676,30 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
       need_masks = std::max(need_masks,
                             level_vertices(last.g) * (last.g.dim == 3 ? 2 : 1));
   }
+  // Beside mode: the finest level, when it is a launch of its own, runs
+  // beside the coarser ones: its classification on `s` while they
+  // (classification and compaction, in order) run on the side stream, its
+  // compaction once they are done, since its list follows theirs.  The
+  // levels are independent unless old vertices are tested against the
+  // previous level (`count`), coarser levels store codes the finest one
+  // overwrites (list codes), a callback reports levels one by one, or kernel
+  // timing wants each kernel alone.  (Running the next level's
+  // classification on `s` too, with its compaction on the side stream, cost
+  // more in cross-stream waits than it overlapped.)
+  int ilast = 0;
+  for (int i = 0; i <= kmax; i = group_end[i]) ilast = i;
+  const bool beside = ilast > 0 && group_end[ilast] == ilast + 1 && !count && !cb &&
+                      !crit_codes && c->timing == 0;
   st = ensure((void **)&c->bits, &c->bits_words, need_words * 8);
   if (!st) st = ensure((void **)&c->counts, &c->counts_n, need_chunks * (int64_t)sizeof(int));
   if (!st) st = ensure((void **)&c->lcodes, &c->lcodes_bytes, need_l);
+  if (!st && beside) {
+    int64_t w, ch, lb;
+    launch_needs(&steps[ilast], 1, false, &w, &ch, &lb);
+    st = ensure((void **)&c->bits2, &c->bits2_words, w * 8);
+    if (!st) st = ensure((void **)&c->counts2, &c->counts2_n, ch * (int64_t)sizeof(int));
+  }
+  if (!st && beside) st = ensure_side(c);
   if (st) return st;
   if (need_masks > c->masks_bytes) {
     hipDeviceSynchronize();
@@ -679,16 +723,28 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
   if (timed && (launch_wait_stamp(nullptr, kTimelineLeadUs, s) != hipSuccess ||
                 hipEventRecord(c->ev_start, s) != hipSuccess))
     return PCRIT_E_HIP;
+  hipStream_t t = s;  // stream of the levels before the finest
+  if (beside) {
+    t = c->side;
+    if (hipEventRecord(c->ev_fork, s) != hipSuccess ||
+        hipStreamWaitEvent(t, c->ev_fork, 0) != hipSuccess)
+      return PCRIT_E_HIP;
+  }
   for (int i = 0; i <= kmax; i = group_end[i]) {
     const int n = group_end[i] - i;
+    const bool finest = i + n > kmax;
     // the compaction of a last launch of one level publishes the offsets
-    const bool pub = publish && i + n > kmax && n == 1;
-    st = enqueue_group(c, s, field, &steps[i], n, codes, crit, crit_codes,
-                       crit_capacity, nullptr, gen, i + n > kmax, c->bits, c->counts,
-                       pub ? publish : nullptr, pub ? kmax + 2 : 0);
+    const bool pub = publish && finest && n == 1;
+    hipStream_t si = beside && !finest ? t : s;
+    if (beside && finest && hipEventRecord(c->ev_join, t) != hipSuccess) return PCRIT_E_HIP;
+    st = enqueue_group(c, si, field, &steps[i], n, codes, crit, crit_codes, crit_capacity,
+                       nullptr, gen, finest, beside && finest ? c->bits2 : c->bits,
+                       beside && finest ? c->counts2 : c->counts, pub ? publish : nullptr,
+                       pub ? kmax + 2 : 0, nullptr, nullptr,
+                       beside && finest ? c->ev_join : nullptr);
     if (pub) *published = true;
     if (st) return st;
-    if (timed && hipEventRecord(c->ev_level[i + n - 1], s) != hipSuccess)
+    if (timed && hipEventRecord(c->ev_level[i + n - 1], si) != hipSuccess)
       return PCRIT_E_HIP;
     if (cb) {
       if (read_status(c, s)) return PCRIT_E_HIP;
@@ -1010,12 +1066,7 @@ int pcrit_progressive_timeline(pcrit_ctx *c, void *hip_stream, const float *fiel
     return PCRIT_E_HIP;
 
   const bool learn = order_mode == 2 && nrl > 0;
-  if (nrl > 0 && !c->side) {
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
-      return PCRIT_E_HIP;
-  }
+  if (nrl > 0 && ensure_side(c)) return PCRIT_E_HIP;
 
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
