@@ -123,3 +123,32 @@ def test_in_captured_graph(dev):
         assert int(cnt.item()) == ref.count, rep
         assert torch.equal(crit[:ref.count], ref.crit), rep
         assert torch.equal(codes, ref.codes), rep
+
+
+@pytest.mark.parametrize("kind", ["checker", "checker_rows", "half"])
+def test_dense_rounds(dev, kind):
+    """Rounds of 64 words with most bits set (checkerboards: most vertices
+    critical) and mixed ones: lists and list codes against the oracle, on
+    full-resolution levels (linear words) and on level 1 (row starts from
+    the word's row)."""
+    ctx = pc.Context(0)
+    shape = (256, 96, 40)
+    x, y, z = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    f = ((-1.0) ** (x + y + z)).astype(np.float32) + 1e-3 * fieldgen.iid_field(shape, 3)
+    if kind == "checker_rows":
+        f = np.where(y % 3 == 0, fieldgen.iid_field(shape, 4), f).astype(np.float32)
+    elif kind == "half":
+        f = np.where(fieldgen.iid_field(shape, 5) < 0.5, f, fieldgen.iid_field(shape, 6))
+        f = f.astype(np.float32)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).to(dev)
+    for level in (0, 1):
+        ref = oracle.classify(f, level=level)
+        log(kind, "level", level, "critical fraction", ref.count / ref.codes.size * (8 if level else 1))
+        r = pc.classify(ft, level, ctx=ctx, with_crit_codes=True)
+        torch.cuda.synchronize()
+        assert r.count == ref.count
+        assert np.array_equal(r.crit.cpu().numpy().view(np.uint32), ref.crit)
+        assert np.array_equal(r.crit_codes.cpu().numpy(), ref.codes.ravel()[ref.crit])
+    p = pc.progressive(ft, ctx=ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(p.level_list(0).cpu().numpy().view(np.uint32), oracle.classify(f).crit)
