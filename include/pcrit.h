@@ -163,11 +163,13 @@ int pcrit_classify_noalloc(pcrit_ctx *ctx, void *hip_stream, const float *field,
 typedef void (*pcrit_level_cb)(int level, int64_t count, void *user);
 
 /* Progressive classification: levels k_max, k_max-1, ..., 0 in turn, each
- * level's list complete before the next level's list is written.  Without a
- * callback, re-classification count or list codes, and with kernel timing
- * off, the finest level's classification runs beside the coarser levels,
+ * level's list complete before the next level's list is written.  When the
+ * caller does not watch the levels complete (no callback, no level times)
+ * and asks for no re-classification count or list codes, and kernel timing
+ * is off, the finest level's classification runs beside the coarser levels,
  * which then run on the context's second stream (forked from and joined
- * back to hip_stream by events; the call's work still ends on hip_stream).
+ * back to hip_stream by events; the call's work still ends on hip_stream):
+ * the call ends sooner, its coarser levels complete later.
  * A vertex already
  * present at level k+1 needs re-classifying at level k only if its polarity
  * mask or its set of absent (off-grid) neighbours changed, i.e. if some new

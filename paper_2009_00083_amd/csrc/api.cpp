@@ -681,15 +681,17 @@ int enqueue_progressive(pcrit_ctx *c, hipStream_t s, const float *field,
   // (classification and compaction, in order) run on the side stream, its
   // compaction once they are done, since its list follows theirs.  The
   // levels are independent unless old vertices are tested against the
-  // previous level (`count`), coarser levels store codes the finest one
-  // overwrites (list codes), a callback reports levels one by one, or kernel
-  // timing wants each kernel alone.  (Running the next level's
-  // classification on `s` too, with its compaction on the side stream, cost
-  // more in cross-stream waits than it overlapped.)
+  // previous level (`count`) or coarser levels store codes the finest one
+  // overwrites (list codes).  Sharing the GPU with the finest level delays
+  // the coarser ones, so a caller that watches levels complete (a callback
+  // or level times) gets them in turn, and so does kernel timing, which
+  // wants each kernel alone.  (Running the next level's classification on
+  // `s` too, with its compaction on the side stream, cost more in
+  // cross-stream waits than it overlapped.)
   int ilast = 0;
   for (int i = 0; i <= kmax; i = group_end[i]) ilast = i;
   const bool beside = ilast > 0 && group_end[ilast] == ilast + 1 && !count && !cb &&
-                      !crit_codes && c->timing == 0;
+                      !timed && !crit_codes && c->timing == 0;
   st = ensure((void **)&c->bits, &c->bits_words, need_words * 8);
   if (!st) st = ensure((void **)&c->counts, &c->counts_n, need_chunks * (int64_t)sizeof(int));
   if (!st) st = ensure((void **)&c->lcodes, &c->lcodes_bytes, need_l);

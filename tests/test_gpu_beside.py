@@ -1,13 +1,14 @@
 """Progressive calls whose finest level runs beside the coarser levels.
 
-Without a callback, re-classification count or list codes, and with kernel
-timing off, the finest level's classification runs on the caller's stream
+When the caller does not watch the levels (no callback, no level times) and
+asks for no re-classification count or list codes, and kernel timing is
+off, the finest level's classification runs on the caller's stream
 while the coarser levels run on the context's second stream, and its
 compaction waits for them.  These cases compare that schedule with the
-serial one (kernel timing on) and with the oracle, through the C ABI, on
-grids whose finest levels take the quad tiles and on grids that do not,
-and replay the asynchronous call (fork and join inside) from a captured
-graph.
+serial one (kernel timing on, or level times) and with the oracle, through
+the C ABI, on grids whose finest levels take the quad tiles and on grids
+that do not, and replay the asynchronous call (fork and join inside) from
+a captured graph.
 """
 import sys
 
@@ -55,10 +56,14 @@ def test_beside_matches_serial_and_oracle(ctx, dev, shape):
     log("beside", shape)
     a = _run(ctx, ft, serial=False)
     b = _run(ctx, ft, serial=True)
-    assert np.array_equal(a.offsets, b.offsets)
+    c = pc.progressive(ft, ctx=ctx, level_times=True)  # watched levels: serial
+    torch.cuda.synchronize()
     n = int(a.offsets[-1])
-    assert torch.equal(a.crit[:n], b.crit[:n])
-    assert torch.equal(a.codes, b.codes)
+    for other in (b, c):
+        assert np.array_equal(a.offsets, other.offsets)
+        assert torch.equal(a.crit[:n], other.crit[:n])
+        assert torch.equal(a.codes, other.codes)
+    assert np.all(np.diff(c.level_ms) >= 0)
     for i, k in enumerate(a.levels):
         ref = oracle.classify(f, level=k)
         got = a.crit[a.offsets[i]:a.offsets[i + 1]].cpu().numpy().view(np.uint32)
