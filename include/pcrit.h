@@ -415,7 +415,10 @@ typedef struct pcrit_batch_field {
  * offsets then hold the required sizes).  Without offsets_host the call
  * launches kernels only (no allocation once the context's scratch has grown
  * to the batch, no memset, no wait), so it can be captured in a HIP graph;
- * calls that overlap on one context race (they share its scratch). */
+ * calls that overlap on one context race (they share its scratch).  With
+ * more than 16 fields a group's compaction runs on the context's second
+ * stream while the next group is classified on hip_stream (events fork and
+ * join the streams; the call's work still ends on hip_stream). */
 int pcrit_classify_batch(pcrit_ctx *ctx, void *hip_stream, int n_fields,
                          const pcrit_batch_field *fields_host, uint32_t *crit,
                          uint8_t *crit_codes, int64_t crit_capacity,

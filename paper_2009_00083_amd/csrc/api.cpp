@@ -128,6 +128,9 @@ struct pcrit_ctx {
   // while the leading levels run, and the events that fork and join it
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // batch pipeline: group g's classification done (ev_cls), its compaction
+  // done (ev_cmp), per scratch set g % 2
+  hipEvent_t ev_cls[2] = {}, ev_cmp[2] = {};
 };
 
 // GPU wait ahead of the first stamp or start event of a timed call
@@ -169,6 +172,10 @@ int ensure_side(pcrit_ctx *c) {
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
     return PCRIT_E_HIP;
+  for (int k = 0; k < 2; k++)
+    if (hipEventCreateWithFlags(&c->ev_cls[k], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_cmp[k], hipEventDisableTiming) != hipSuccess)
+      return PCRIT_E_HIP;
   return PCRIT_OK;
 }
 
@@ -244,7 +251,8 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
                   unsigned gen, bool final_group, uint64_t *bits, int *counts,
                   int64_t *publish = nullptr, int publish_n = 0,
                   const RegionHooks *rh = nullptr, int64_t *lbase = nullptr,
-                  hipEvent_t compact_after = nullptr) {
+                  hipEvent_t compact_after = nullptr, hipStream_t compact_st = nullptr,
+                  hipEvent_t classified = nullptr) {
   const bool fused = n > 1;
   const int dim = steps[0].g.dim;
   int64_t total_words = 0;
@@ -374,6 +382,14 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
   // the lists of earlier launches that ran on another stream come first
   if (compact_after && hipStreamWaitEvent(st, compact_after, 0) != hipSuccess)
     return PCRIT_E_HIP;
+  // or the compaction runs on another stream once the classification is
+  // done (`classified` recorded here)
+  if (compact_st) {
+    if (hipEventRecord(classified, st) != hipSuccess ||
+        hipStreamWaitEvent(compact_st, classified, 0) != hipSuccess)
+      return PCRIT_E_HIP;
+    st = compact_st;
+  }
   record_kernel(c, 1, tlevel, 0, st);
   if (launch_compact(b, small, st) != hipSuccess) return PCRIT_E_HIP;
   record_kernel(c, 1, tlevel, 1, st);
@@ -509,6 +525,10 @@ void pcrit_destroy(pcrit_ctx *c) {
   if (c->side) hipStreamDestroy(c->side);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
+  for (int k = 0; k < 2; k++) {
+    if (c->ev_cls[k]) hipEventDestroy(c->ev_cls[k]);
+    if (c->ev_cmp[k]) hipEventDestroy(c->ev_cmp[k]);
+  }
   if (c->h_status) hipHostFree(c->h_status);
   if (c->ev_start) hipEventDestroy(c->ev_start);
   for (int i = 0; i <= kMaxLevels; i++)
@@ -1206,8 +1226,16 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
   }
   if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
   hipStream_t s = (hipStream_t)hip_stream;
+  // More than one group: group g+1 is classified on hip_stream while group
+  // g is compacted on the side stream (compactions in order there, so the
+  // lists still land in field order), each group on scratch set g % 2.
+  const int ngroups = (n_fields + kMaxFused - 1) / kMaxFused;
+  const bool piped = ngroups > 1;
   int st = ensure((void **)&c->bits, &c->bits_words, words * 8);
   if (!st) st = ensure((void **)&c->counts, &c->counts_n, chunks * (int64_t)sizeof(int));
+  if (!st && piped) st = ensure((void **)&c->bits2, &c->bits2_words, words * 8);
+  if (!st && piped) st = ensure((void **)&c->counts2, &c->counts2_n, chunks * (int64_t)sizeof(int));
+  if (!st && piped) st = ensure_side(c);
   int64_t *off = offsets_dev;
   if (!st && !off) {
     st = ensure((void **)&c->boff, &c->boff_bytes, 8 * (int64_t)(n_fields + 1));
@@ -1219,13 +1247,22 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
   if (launch_zero_i64(off, 1, s) != hipSuccess) return PCRIT_E_HIP;
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
-  for (int i0 = 0; i0 < n_fields; i0 += kMaxFused) {
+  for (int i0 = 0, g = 0; i0 < n_fields; i0 += kMaxFused, g++) {
     const int n = std::min(kMaxFused, n_fields - i0);
+    const int k = g & 1;
+    // set k is free once group g-2's compaction is done
+    if (piped && g >= 2 && hipStreamWaitEvent(s, c->ev_cmp[k], 0) != hipSuccess)
+      return PCRIT_E_HIP;
     st = enqueue_group(c, s, steps[(size_t)i0].f, &steps[(size_t)i0], n, steps[(size_t)i0].codes,
-                       crit, crit_codes, crit_capacity, nullptr, gen, true, c->bits, c->counts,
-                       nullptr, 0, nullptr, off);
+                       crit, crit_codes, crit_capacity, nullptr, gen, true,
+                       k ? c->bits2 : c->bits, k ? c->counts2 : c->counts, nullptr, 0, nullptr,
+                       off, nullptr, piped ? c->side : nullptr, piped ? c->ev_cls[k] : nullptr);
     if (st) return st;
+    if (piped && hipEventRecord(c->ev_cmp[k], c->side) != hipSuccess) return PCRIT_E_HIP;
   }
+  if (piped && (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
+                hipStreamWaitEvent(s, c->ev_join, 0) != hipSuccess))
+    return PCRIT_E_HIP;
   if (!offsets_host) return PCRIT_OK;
   if (hipMemcpyAsync(offsets_host, off, 8 * (size_t)(n_fields + 1), hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
