@@ -167,15 +167,17 @@ int ensure(void **p, int64_t *have, int64_t bytes) {
 // The context's second stream (default priority) and the events that fork
 // work onto it and join it back.
 int ensure_side(pcrit_ctx *c) {
-  if (c->side) return PCRIT_OK;
-  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+  if (!c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    c->side = nullptr;
     return PCRIT_E_HIP;
-  for (int k = 0; k < 2; k++)
-    if (hipEventCreateWithFlags(&c->ev_cls[k], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_cmp[k], hipEventDisableTiming) != hipSuccess)
+  }
+  hipEvent_t *evs[6] = {&c->ev_fork, &c->ev_join, &c->ev_cls[0], &c->ev_cls[1],
+                        &c->ev_cmp[0], &c->ev_cmp[1]};
+  for (hipEvent_t *e : evs)
+    if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+      *e = nullptr;
       return PCRIT_E_HIP;
+    }
   return PCRIT_OK;
 }
 
