@@ -1,0 +1,137 @@
+"""Pins of the LTS Step 1 oracle (superlevel / sublevel set propagation
+from each extremum, Sections 4.2 and 4.5): an independent breadth-first
+definition of the component, the saddle's properties, the persistence rule,
+closed forms, and the symmetry of minima and maxima."""
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle
+from oracle import lts
+from oracle.order import extrema, order_field
+
+
+def _fields():
+    yield fieldgen.iid_field((9, 8, 7), 3)
+    yield fieldgen.gaussian_field((12, 10, 9), 4, 5, noise=("uniform", 2e-2))
+    yield fieldgen.iid_field((13, 11), 5)
+    yield fieldgen.tie_field((8, 9, 6), 6, 3)
+
+
+@pytest.mark.parametrize("maxima", [True, False])
+def test_saddle_stop_is_the_superlevel_component(maxima):
+    """For every stop at a saddle s: the vertices taken are exactly the
+    component of the strict superlevel set {u : key(u) > key(s)} that
+    contains the extremum, together with s (at the level of s itself the
+    component joins the one beyond s); s is the smallest of them and has a
+    larger neighbour outside."""
+    checked = 0
+    for f in _fields():
+        codes = oracle.classify(f).codes
+        mn, mx = extrema(codes)
+        rank, _ = order_field(f)
+        key = rank.astype(np.int64) if maxima else rank.size - 1 - rank.astype(np.int64)
+        for m in (mx if maxima else mn):
+            st, s, comp = lts.propagate_set(f, key, f.shape, int(m), np.inf, 400, 4000, maxima)
+            assert st in (lts.SADDLE, lts.BUDGET)
+            if st != lts.SADDLE:
+                continue
+            assert comp == lts.superlevel_component(f.shape, key, int(m), key[s] + 1) | {s}
+            assert key[s] == min(key[c] for c in comp)
+            assert any(u not in comp and key[u] > key[s] for u in lts.neighbours(f.shape, s))
+            checked += 1
+    assert checked > 50
+
+
+def test_persistence_rule():
+    """With a finite epsilon an extremum stops at the same saddle if the
+    value difference to it is at most epsilon, and is persistent
+    otherwise (the difference grows along the propagation)."""
+    f = fieldgen.gaussian_field((12, 11, 10), 8, 6, noise=("uniform", 3e-2))
+    codes = oracle.classify(f).codes
+    _, mx = extrema(codes)
+    st0, sd0, _ = lts.propagate_all(f, mx, np.inf, max_visited=500, max_frontier=5000)
+    fv = f.ravel()
+    for eps in (0.0, 0.01, 0.03, 0.1):
+        st, sd, _ = lts.propagate_all(f, mx, eps, max_visited=500, max_frontier=5000)
+        for i, m in enumerate(mx):
+            if st0[i] != lts.SADDLE:
+                continue
+            d = np.float32(fv[m] - fv[sd0[i]])
+            if d <= np.float32(eps):
+                assert st[i] == lts.SADDLE and sd[i] == sd0[i]
+            else:
+                assert st[i] == lts.PERSISTENT and sd[i] == -1
+
+
+def test_two_bumps_closed_form():
+    """2D, two peaks on the line y = 3 joined through a pass at x = 5: the
+    lower peak's propagation stops at the pass, after taking the 21
+    vertices of columns 2..4 and the pass itself."""
+    g = np.array([0, 0.5, 1, 0.7, 0.6, 0.5, 1.2, 1.6, 2, 1.5, 1], np.float32)
+    ny, cy = 7, 3
+    y = np.arange(ny)[:, None]
+    f = (g[None, :] - 0.01 * np.abs(y - cy)).astype(np.float32)
+    rank, _ = order_field(f)
+    st, s, comp = lts.propagate_set(f, rank.astype(np.int64), f.shape, cy * 11 + 2, np.inf, 100, 1000)
+    assert st == lts.SADDLE and s == cy * 11 + 5 and len(comp) == 22
+    # the higher peak meets no larger component: it runs to the budget
+    st2, s2, comp2 = lts.propagate_set(f, rank.astype(np.int64), f.shape, cy * 11 + 8, np.inf, 30, 1000)
+    assert st2 == lts.BUDGET and s2 == -1 and len(comp2) == 30
+    # with epsilon below the height above the pass (0.5) the lower peak is
+    # persistent, at or above it not
+    assert lts.propagate(f, rank.astype(np.int64), f.shape, cy * 11 + 2, 0.49, 100, 1000)[0] == lts.PERSISTENT
+    assert lts.propagate(f, rank.astype(np.int64), f.shape, cy * 11 + 2, 0.5, 100, 1000)[:2] == (lts.SADDLE, cy * 11 + 5)
+
+
+def test_single_bump_has_no_saddle():
+    z, y, x = np.meshgrid(np.arange(7), np.arange(8), np.arange(9), indexing="ij")
+    f = -((x - 4.2) ** 2 + (y - 3.7) ** 2 + (z - 3.1) ** 2).astype(np.float32)
+    codes = oracle.classify(f).codes
+    _, mx = extrema(codes)
+    assert len(mx) == 1
+    st, sd, vi = lts.propagate_all(f, mx, np.inf, max_visited=40, max_frontier=1000)
+    assert st[0] == lts.BUDGET and sd[0] == -1 and vi[0] == 40
+
+
+def test_minima_are_maxima_of_negated_field():
+    f = fieldgen.iid_field((10, 9, 8), 11)  # no equal values: the orders reverse exactly
+    mn, _ = extrema(oracle.classify(f).codes)
+    _, mx_neg = extrema(oracle.classify(-f).codes)
+    assert np.array_equal(mn, mx_neg)
+    a = lts.propagate_all(f, mn, 0.05, maxima=False)
+    b = lts.propagate_all(-f, mx_neg, 0.05, maxima=True)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_budget_limits():
+    f = fieldgen.gaussian_field((14, 12, 10), 2, 3, noise=("uniform", 1e-4))
+    _, mx = extrema(oracle.classify(f).codes)
+    st, sd, vi = lts.propagate_all(f, mx, np.inf, max_visited=8, max_frontier=64)
+    assert np.all(vi <= 8)
+    assert np.all((st == lts.BUDGET) | (st == lts.SADDLE))
+    assert np.all(sd[st == lts.BUDGET] == -1)
+
+
+def test_neighbourhood_matches_the_classifier():
+    """The propagation's neighbours are the link vertices of the classifier
+    (its C code has its own offsets): a vertex whose neighbours are all
+    smaller (larger) in the order is exactly a maximum (minimum) of the
+    codes, in 3D and 2D, boundary vertices included."""
+    for f in (fieldgen.iid_field((7, 6, 5), 21), fieldgen.iid_field((9, 8), 22),
+              fieldgen.tie_field((6, 7, 5), 23, 2)):
+        mn, mx = extrema(oracle.classify(f).codes)
+        rank, _ = order_field(f)
+        top = [v for v in range(f.size)
+               if all(rank[u] < rank[v] for u in lts.neighbours(f.shape, v))]
+        bottom = [v for v in range(f.size)
+                  if all(rank[u] > rank[v] for u in lts.neighbours(f.shape, v))]
+        assert np.array_equal(np.array(top, np.uint32), mx)
+        assert np.array_equal(np.array(bottom, np.uint32), mn)
+        # and the neighbourhood is symmetric, 14 (6) vertices inside
+        for v in range(f.size):
+            for u in lts.neighbours(f.shape, v):
+                assert v in lts.neighbours(f.shape, u)
+        centre = int(np.ravel_multi_index(tuple(n // 2 for n in f.shape), f.shape))
+        assert len(lts.neighbours(f.shape, centre)) == (14 if f.ndim == 3 else 6)
