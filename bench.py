@@ -18,7 +18,10 @@ in the learned order (the order network trained, untimed, on held-out
 fields), on this field and on the smooth recipe at 512^3; "batch": 200
 independent fields of 33..257 samples per axis classified with shared
 launches against one call per field; "order_field": the order field
-(ranks by value, ties by index) and extremum lists of the bench field; the
+(ranks by value, ties by index) and extremum lists of the bench field;
+"lts_step1": the superlevel / sublevel set propagation from every maximum
+and minimum of the bench field (Step 1 of the simplification, with the
+persistence test at two epsilons); the
 direct level-0 rate; per-level rates; the roofline of the dominant kernel; and the CPU
 oracle's rate on bounded samples of the same workload (all threads of this
 process's share, and one thread).
@@ -214,6 +217,36 @@ def order_measure(pc, ctx, ft, codes, reps=5):
             "order_field_frac": round(gbs / HBM_PEAK_GBS, 4),
             "extrema_ms": round(ems, 3), "minima": int(mn.numel()), "maxima": int(mx.numel()),
             "note": "both calls wait for the stream; times include the host wait"}
+
+
+def lts_measure(pc, ctx, ft, codes, reps=5):
+    """LTS Step 1 on the bench field: from every maximum and every minimum,
+    the propagation to its saddle, with the persistence test at epsilon
+    0.01 (about the noise's standard deviation) and 0.05, budget 16
+    vertices taken / 64 waiting.  Inputs (order field, extremum lists) are
+    computed first and not timed."""
+    import torch
+    rank, _ = pc.order_field(ft, ctx=ctx)
+    mn, mx = pc.extrema(codes, ctx=ctx)
+    torch.cuda.synchronize()
+    out = {"maxima": int(mx.numel()), "minima": int(mn.numel()), "budget": [16, 64]}
+    for eps in (0.01, 0.05):
+        row = {}
+        for kind, ext, up in (("max", mx, True), ("min", mn, False)):
+            pc.lts_propagate(ft, rank, ext, maxima=up, epsilon=eps, ctx=ctx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st, sd, vi = pc.lts_propagate(ft, rank, ext, maxima=up, epsilon=eps, ctx=ctx)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            cnt = np.bincount(st.cpu().numpy(), minlength=4)
+            row[kind] = {"ms": round(ms, 3), "mprop_per_s": round(ext.numel() / (ms * 1e-3) / 1e6, 1),
+                         "saddle": int(cnt[0]), "persistent": int(cnt[1]), "budget": int(cnt[2]),
+                         "mean_visited": round(float(vi.float().mean().item()), 2)}
+        out[f"eps_{eps}"] = row
+    out["note"] = "one propagation per extremum, not merged at shared saddles; times include the host wait"
+    return out
 
 
 def _region_of(points, shape, edge):
@@ -520,6 +553,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_measure(pc, ctx, dev)
         out["order_field"] = order_measure(pc, ctx, ft, codes)
+        out["lts_step1"] = lts_measure(pc, ctx, ft, codes)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -448,6 +448,45 @@ int pcrit_order_field(pcrit_ctx *ctx, void *hip_stream, const float *field, int6
 int pcrit_extrema(pcrit_ctx *ctx, void *hip_stream, const uint8_t *codes, int64_t nx,
                   int64_t ny, int64_t nz, uint32_t *out, int64_t capacity, int64_t *counts_host);
 
+/* ------------------------------------------------------------------------
+ * Step 1 of localized topological simplification (the scope table's
+ * fourth "next" row, started): the superlevel / sublevel set propagation
+ * from each extremum (Section 4.2, step 1) with the persistence test of
+ * Section 4.5.
+ * ---------------------------------------------------------------------- */
+#define PCRIT_LTS_SADDLE 0     /* stopped at the saddle where it meets another component */
+#define PCRIT_LTS_PERSISTENT 1 /* value difference to the extremum exceeded epsilon */
+#define PCRIT_LTS_BUDGET 2     /* component or waiting set outgrew the budget */
+#define PCRIT_LTS_INVALID 3    /* the listed index is not a vertex of the grid */
+#define PCRIT_LTS_MAX_VISITED 32
+#define PCRIT_LTS_MAX_FRONTIER 128
+
+/* For each extremum ext[i] (device, n_extrema uint32 full-resolution
+ * indices; maxima when maxima != 0, else minima) of the field (device,
+ * float32, nx*ny*nz) with order field rank (device, as pcrit_order_field
+ * writes it): grow the extremum's component one vertex at a time, always
+ * taking the largest vertex in the order (the smallest for minima) adjacent
+ * to it, among the Freudenthal neighbours of pcrit_classify.  Stop when the
+ * vertex just taken
+ *   - differs from the extremum by more than epsilon in value (float32,
+ *     f(m) - f(v) for maxima, f(v) - f(m) for minima): PCRIT_LTS_PERSISTENT;
+ *   - has a larger (smaller) neighbour outside the component: it is the
+ *     saddle, PCRIT_LTS_SADDLE;
+ * or PCRIT_LTS_BUDGET once the component holds max_visited vertices (2 ..
+ * PCRIT_LTS_MAX_VISITED) or more than max_frontier (14 ..
+ * PCRIT_LTS_MAX_FRONTIER) vertices wait outside it.  Outputs (device,
+ * n_extrema entries each): status (uint8), saddle (int32 index, -1 unless
+ * a saddle stop) and visited (uint16, vertices taken, the extremum
+ * included).  Every extremum propagates on its own (propagations that meet
+ * at a saddle are not merged).  Asynchronous: kernels only, no wait.
+ * PCRIT_E_ARG for NULL or misaligned pointers, a NaN epsilon or budgets
+ * out of range; dims as for pcrit_classify. */
+int pcrit_lts_propagate(pcrit_ctx *ctx, void *hip_stream, const float *field,
+                        const uint32_t *rank, int64_t nx, int64_t ny, int64_t nz,
+                        const uint32_t *extrema, int64_t n_extrema, int maxima, float epsilon,
+                        int max_visited, int max_frontier, uint8_t *status, int32_t *saddle,
+                        uint16_t *visited);
+
 #ifdef __cplusplus
 }
 #endif

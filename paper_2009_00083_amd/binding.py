@@ -32,7 +32,8 @@ EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_preview_f1_levels", "pcrit_mlp_feature_level", "pcrit_mlp_features",
             "pcrit_mlp_labels", "pcrit_mlp_forward", "pcrit_mlp_backward",
             "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline",
-            "pcrit_classify_batch", "pcrit_order_field", "pcrit_extrema")
+            "pcrit_classify_batch", "pcrit_order_field", "pcrit_extrema",
+            "pcrit_lts_propagate")
 MLP_PARAMS = 6337
 MLP_INPUTS = 32
 
@@ -81,6 +82,9 @@ def _load():
     lib.pcrit_order_field.restype = i32
     lib.pcrit_extrema.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
     lib.pcrit_extrema.restype = i32
+    lib.pcrit_lts_propagate.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, i64, i32,
+                                        ctypes.c_float, i32, i32, vp, vp, vp]
+    lib.pcrit_lts_propagate.restype = i32
     lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
     lib.NULL_CB = ctypes.cast(None, lib.LEVEL_CB)
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
@@ -436,6 +440,35 @@ def extrema(codes, *, ctx: Optional[Context] = None, capacity: Optional[int] = N
                                  _ptr(out), cap, cnt.ctypes.data), "pcrit_extrema")
     a, b = int(cnt[0]), int(cnt[1])
     return out[:a], out[a:a + b]
+
+
+LTS_SADDLE, LTS_PERSISTENT, LTS_BUDGET, LTS_INVALID = 0, 1, 2, 3
+LTS_MAX_VISITED, LTS_MAX_FRONTIER = 32, 128
+
+
+def lts_propagate(field, rank, extrema_list, *, maxima: bool = True,
+                  epsilon: float = float("inf"), max_visited: int = 16, max_frontier: int = 64,
+                  ctx: Optional[Context] = None, stream=None):
+    """Step 1 of localized topological simplification: the superlevel
+    (maxima) or sublevel (minima) set propagation from each listed extremum,
+    with the persistence test.  ``rank`` is the order field (int32 tensor as
+    order_field returns it), ``extrema_list`` int32 full-resolution indices.
+    Returns (status uint8, saddle int32, visited int16) tensors, one entry
+    per extremum; asynchronous on the stream."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    c = _ctx_for(field, ctx)
+    check_buffer("rank", rank, torch.int32, field.device, numel=field.numel())
+    check_buffer("extrema", extrema_list, torch.int32, field.device)
+    n = extrema_list.numel()
+    status = torch.empty(max(n, 1), dtype=torch.uint8, device=field.device)
+    saddle = torch.empty(max(n, 1), dtype=torch.int32, device=field.device)
+    visited = torch.empty(max(n, 1), dtype=torch.int16, device=field.device)
+    _check(_load().pcrit_lts_propagate(
+        c.handle, _stream_handle(field, stream), _ptr(field), _ptr(rank), nx, ny, nz,
+        _ptr(extrema_list), n, 1 if maxima else 0, float(epsilon), int(max_visited),
+        int(max_frontier), _ptr(status), _ptr(saddle), _ptr(visited)), "pcrit_lts_propagate")
+    return status[:n], saddle[:n], visited[:n]
 
 
 def classify_noalloc(field, level: int, codes, crit, *, ctx: Context,

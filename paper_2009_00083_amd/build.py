@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libpcrit.so")
 SOURCES = ["csrc/classify.hip", "csrc/api.cpp", "csrc/link_table.cpp",
            "csrc/metrics.cpp", "csrc/noalloc.hip", "csrc/classify_quad.hip",
-           "csrc/learned.hip", "csrc/order.hip"]
+           "csrc/learned.hip", "csrc/order.hip", "csrc/lts.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-result", "-Wno-unused-value",
          # keep the compiler from forming packed fp32 instructions

@@ -1348,4 +1348,28 @@ int pcrit_extrema(pcrit_ctx *c, void *hip_stream, const uint8_t *codes, int64_t 
   counts_host[1] = off[2] - off[1];
   return off[2] > capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
 }
+
+int pcrit_lts_propagate(pcrit_ctx *c, void *hip_stream, const float *field,
+                        const uint32_t *rank, int64_t nx, int64_t ny, int64_t nz,
+                        const uint32_t *extrema, int64_t n_extrema, int maxima, float epsilon,
+                        int max_visited, int max_frontier, uint8_t *status, int32_t *saddle,
+                        uint16_t *visited) {
+  static_assert(PCRIT_LTS_MAX_VISITED == kLtsMaxVisited && PCRIT_LTS_MAX_FRONTIER == kLtsMaxFrontier,
+                "budget limits");
+  if (!c || !field || !rank || n_extrema < 0 ||
+      (n_extrema > 0 && (!extrema || !status || !saddle || !visited)) ||
+      misaligned(field, 4) || misaligned(rank, 4) || (extrema && misaligned(extrema, 4)) ||
+      (saddle && misaligned(saddle, 4)) || (visited && misaligned(visited, 2)) ||
+      epsilon != epsilon || max_visited < 2 || max_visited > PCRIT_LTS_MAX_VISITED ||
+      max_frontier < 14 || max_frontier > PCRIT_LTS_MAX_FRONTIER)
+    return PCRIT_E_ARG;
+  const int st = check_dims(nx, ny, nz);
+  if (st) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  return launch_lts_propagate(field, rank, nx, ny, nz, extrema, n_extrema, maxima != 0, epsilon,
+                              max_visited, max_frontier, status, saddle, visited,
+                              (hipStream_t)hip_stream) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
 }  // extern "C"
