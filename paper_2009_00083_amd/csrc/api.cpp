@@ -11,6 +11,7 @@
 
 #include "../../include/pcrit.h"
 #include "pcrit_internal.h"
+#include "lts.h"
 
 using namespace pcrit;
 

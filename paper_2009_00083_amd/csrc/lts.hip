@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "pcrit_internal.h"
+#include "lts.h"
 
 namespace pcrit {
 namespace {

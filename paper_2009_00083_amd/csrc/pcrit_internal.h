@@ -324,17 +324,6 @@ hipError_t launch_stamp(uint64_t *out, hipStream_t st);
 // Zeroes n int64 values with a kernel (a memset node misbehaves in captured
 // graphs).
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t st);
-// LTS Step 1: the superlevel (maxima) or sublevel (minima) set propagation
-// from each extremum ext[0 .. n_ext) of a grid with order field `rank`;
-// per extremum a status (kLts*), the saddle (or -1) and the vertices taken.
-constexpr int kLtsMaxVisited = 32;    // largest max_visited
-constexpr int kLtsMaxFrontier = 128;  // largest max_frontier
-constexpr uint8_t kLtsSaddle = 0, kLtsPersistent = 1, kLtsBudget = 2, kLtsInvalid = 3;
-hipError_t launch_lts_propagate(const float *f, const uint32_t *rank, int64_t nx, int64_t ny,
-                                int64_t nz, const uint32_t *ext, int64_t n_ext, bool maxima,
-                                float eps, int max_visited, int max_frontier, uint8_t *status,
-                                int32_t *saddle, uint16_t *visited, hipStream_t st);
-
 
 // Order field (order.hip): rank[i] of every sample by (value, index) and the
 // sample at each rank (sorted, also the sort's value buffer); scratch of
