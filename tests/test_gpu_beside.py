@@ -48,7 +48,8 @@ def _run(ctx, ft, serial):
     return p
 
 
-@pytest.mark.parametrize("shape", [(256, 192, 160), (130, 66, 97), (96, 80, 1), (64, 64, 64)])
+@pytest.mark.parametrize("shape", [(256, 192, 160), (130, 66, 97), (96, 80, 1), (2200, 2000, 1),
+                                   (64, 64, 64)])
 def test_beside_matches_serial_and_oracle(ctx, dev, shape):
     f = fieldgen.gaussian_field(shape, 17, 6, noise=("uniform", 1e-3)) if shape[2] > 1 else \
         fieldgen.iid_field(shape[:2], 17)
