@@ -135,3 +135,136 @@ def test_neighbourhood_matches_the_classifier():
                 assert v in lts.neighbours(f.shape, u)
         centre = int(np.ravel_multi_index(tuple(n // 2 for n in f.shape), f.shape))
         assert len(lts.neighbours(f.shape, centre)) == (14 if f.ndim == 3 else 6)
+
+
+def _elder_pairs(shape, key):
+    """0-dimensional superlevel-set persistence pairs by the elder rule: sweep
+    the vertices from the largest key down with a union-find of the swept
+    ones; where components meet, every one but the component of the largest
+    maximum dies, paired with the meeting vertex.  {maximum: saddle}; the
+    global maximum stays unpaired."""
+    parent, top, pairs = {}, {}, {}
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for v in np.argsort(-key, kind="stable"):
+        v = int(v)
+        roots = {find(u) for u in lts.neighbours(shape, v) if u in parent}
+        parent[v] = v
+        if not roots:
+            top[v] = v
+            continue
+        best = max(roots, key=lambda r: key[top[r]])
+        for r in roots:
+            if r != best:
+                pairs[top[r]] = v
+            parent[r] = best
+        parent[v] = best
+    return pairs
+
+
+def _merged_fields():
+    yield fieldgen.gaussian_field((12, 10, 9), 4, 5, noise=("uniform", 2e-2))
+    yield fieldgen.iid_field((8, 7, 6), 13)
+    yield fieldgen.tie_field((8, 9, 6), 6, 3)
+    yield fieldgen.gaussian_field((30, 26), 7, 4, noise=("uniform", 5e-2))
+
+
+@pytest.mark.parametrize("maxima", [True, False])
+def test_merged_removes_exactly_the_elder_pairs_within_epsilon(maxima):
+    """Merged propagations from every maximum (minimum), budgets unbounded:
+    an extremum is removed, at saddle s, exactly when the elder rule pairs
+    it with s and the value difference is at most epsilon; every other one
+    is persistent; a removed extremum's component is the strict superlevel
+    component of s plus s.  The independent propagations differ on some
+    extrema (the elder one at a saddle), so the merging is exercised."""
+    differs = 0
+    for f in _merged_fields():
+        fv = f.ravel()
+        rank, _ = order_field(f)
+        key = rank.astype(np.int64) if maxima else rank.size - 1 - rank.astype(np.int64)
+        mn, mx = extrema(oracle.classify(f).codes)
+        ext = mx if maxima else mn
+        pairs = _elder_pairs(f.shape, key)
+        assert set(pairs) | {int(np.argmax(key))} == set(int(m) for m in ext)
+        big = f.size + 1
+        for eps in (0.0, 0.01, 0.05, 0.3, np.inf):
+            st, sd, vi = lts.propagate_merged(f, ext, eps, maxima, big, big, rank=rank)
+            for i, m in enumerate(ext):
+                m = int(m)
+                s = pairs.get(m)
+                d = None if s is None else (np.float32(fv[m] - fv[s]) if maxima else
+                                            np.float32(fv[s] - fv[m]))
+                if s is not None and d <= np.float32(eps):
+                    assert (st[i], sd[i]) == (lts.SADDLE, s), (m, eps)
+                    comp = lts.superlevel_component(f.shape, key, m, key[s] + 1)
+                    assert vi[i] == len(comp) + 1
+                else:
+                    assert (st[i], sd[i]) == (lts.PERSISTENT, -1), (m, eps)
+            ind = lts.propagate_all(f, ext, eps, maxima, big, big, rank=rank)
+            differs += int(np.count_nonzero(ind[0] != st))
+    assert differs > 0
+
+
+def test_merged_result_does_not_depend_on_arrival_order():
+    """Budgets small enough to stop some merges: any order of starting the
+    propagations gives the same statuses, saddles and counts."""
+    f = fieldgen.gaussian_field((14, 12, 10), 9, 4, noise=("uniform", 3e-2))
+    _, mx = extrema(oracle.classify(f).codes)
+    rng = np.random.default_rng(5)
+    for mv, mf, eps in ((8, 40, 0.05), (32, 128, 0.1), (16, 64, np.inf)):
+        ref = lts.propagate_merged(f, mx, eps, True, mv, mf)
+        assert np.count_nonzero(ref[0] == lts.SADDLE) > 0
+        for _ in range(3):
+            got = lts.propagate_merged(f, mx, eps, True, mv, mf, order=rng.permutation(len(mx)))
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b)
+
+
+def test_merged_two_bumps_and_chain_closed_form():
+    """2D profiles along x, constant bands in y with a small slope towards
+    the middle row.  Two peaks joined at a pass: with epsilon at or above
+    the lower peak's height over the pass it is removed there and the higher
+    one is persistent (with no epsilon its propagation takes the whole grid).  Three peaks
+    (1.0, 2.0, 1.5) with passes 0.6 and 0.9: the peak 1.5 first merges into
+    the peak 2.0's component at the pass 0.9; with epsilon 0.7 both lower
+    peaks go and the merged propagation, led by 2.0, stops as persistent."""
+    ny, cy = 7, 3
+    y = np.arange(ny)[:, None]
+
+    def grid(g):
+        return (np.asarray(g, np.float32)[None, :] - 0.01 * np.abs(y - cy)).astype(np.float32)
+
+    f = grid([0, 0.5, 1, 0.7, 0.6, 0.5, 1.2, 1.6, 2, 1.5, 1])
+    big = f.size + 1
+    pk = [cy * 11 + 2, cy * 11 + 8]
+    st, sd, vi = lts.propagate_merged(f, pk, 0.5, True, big, big)
+    assert list(st) == [lts.SADDLE, lts.PERSISTENT] and sd[0] == cy * 11 + 5
+    st, sd, vi = lts.propagate_merged(f, pk, np.inf, True, big, big)
+    assert list(st) == [lts.SADDLE, lts.PERSISTENT] and list(vi) == [22, f.size]
+    st, sd, _ = lts.propagate_merged(f, pk, 0.49, True, big, big)
+    assert list(st) == [lts.PERSISTENT, lts.PERSISTENT]
+
+    g = [0, 1.0, 0.6, 2.0, 0.9, 1.5, 0.2]
+    f = grid(g)
+    n = len(g)
+    pk = [cy * n + 1, cy * n + 3, cy * n + 5]
+    st, sd, _ = lts.propagate_merged(f, pk, 0.7, True, big, big)
+    assert list(st) == [lts.SADDLE, lts.PERSISTENT, lts.SADDLE]
+    assert list(sd) == [cy * n + 2, -1, cy * n + 4]
+    # epsilon 0.45: the peak 1.0 goes (0.4), 1.5 stays (0.6)
+    st, sd, _ = lts.propagate_merged(f, pk, 0.45, True, big, big)
+    assert list(st) == [lts.SADDLE, lts.PERSISTENT, lts.PERSISTENT]
+
+
+def test_merged_invalid_entries():
+    f = fieldgen.iid_field((9, 8, 7), 3)
+    _, mx = extrema(oracle.classify(f).codes)
+    notmax = next(v for v in range(f.size) if v not in set(mx.tolist()))
+    st, sd, vi = lts.propagate_merged(f, [int(mx[0]), f.size, notmax, int(mx[1])], 0.1)
+    assert list(st[1:3]) == [lts.INVALID, lts.INVALID] and list(sd[1:3]) == [-1, -1]
+    assert list(vi[1:3]) == [0, 0]
