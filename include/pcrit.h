@@ -384,7 +384,7 @@ int pcrit_progressive_timeline(pcrit_ctx *ctx, void *hip_stream, const float *fi
                                double *level_ms_host, double *region_ms_host);
 
 /* ------------------------------------------------------------------------
- * Batches of independent fields (the scope table's second "next" row).
+ * Batches of independent fields.
  *
  * Every field of the batch is classified at level 0 exactly as
  * pcrit_classify would (Section 3.1, ties by index within the field), but
@@ -425,7 +425,7 @@ int pcrit_classify_batch(pcrit_ctx *ctx, void *hip_stream, int n_fields,
                          int64_t *offsets_host, int64_t *offsets_dev);
 
 /* ------------------------------------------------------------------------
- * Order field and extremum lists (the scope table's third "next" row: the
+ * Order field and extremum lists (the
  * inputs of the paper's simplification).
  * ---------------------------------------------------------------------- */
 
@@ -449,10 +449,10 @@ int pcrit_extrema(pcrit_ctx *ctx, void *hip_stream, const uint8_t *codes, int64_
                   int64_t ny, int64_t nz, uint32_t *out, int64_t capacity, int64_t *counts_host);
 
 /* ------------------------------------------------------------------------
- * Step 1 of localized topological simplification (the scope table's
- * fourth "next" row, started): the superlevel / sublevel set propagation
- * from each extremum (Section 4.2, step 1) with the persistence test of
- * Section 4.5.
+ * Step 1 of localized topological simplification: the superlevel /
+ * sublevel set propagation from each extremum (Section 4.2, step 1) with
+ * the persistence test of Section 4.5, on its own or merged at saddles
+ * (Section 4.4).
  * ---------------------------------------------------------------------- */
 #define PCRIT_LTS_SADDLE 0     /* stopped at the saddle where it meets another component */
 #define PCRIT_LTS_PERSISTENT 1 /* value difference to the extremum exceeded epsilon */
@@ -486,6 +486,37 @@ int pcrit_lts_propagate(pcrit_ctx *ctx, void *hip_stream, const float *field,
                         const uint32_t *extrema, int64_t n_extrema, int maxima, float epsilon,
                         int max_visited, int max_frontier, uint8_t *status, int32_t *saddle,
                         uint16_t *visited);
+
+/* Merged propagations (Sections 4.4 and 4.5): the propagations of the
+ * listed extrema (distinct vertices; maxima when maxima != 0, else minima)
+ * grow as in pcrit_lts_propagate, each led by its extremum, but meet at
+ * saddles.  A propagation that stops at a saddle s adds the higher (lower,
+ * for minima) neighbours of s it holds to s's arrival count; the one whose
+ * addition makes the count equal s's number of such neighbours goes on
+ * from s with the union of every component that arrived there, led by the
+ * largest (smallest) of their leaders, whose value the persistence test
+ * then uses.  The leaders of the other arrived components are paired with
+ * s: status PCRIT_LTS_SADDLE, saddle s, visited = the size of the component
+ * they led.  A leader whose component stopped at a saddle that no later
+ * arrival completes stays paired with it.  PCRIT_LTS_PERSISTENT when the
+ * persistence test stops the propagation it leads (or when it takes the
+ * whole grid); PCRIT_LTS_BUDGET when that propagation outgrows the budgets
+ * of pcrit_lts_propagate, a merge included (union of max_visited vertices
+ * or more, or more than max_frontier waiting; visited is then the union's
+ * size); PCRIT_LTS_INVALID for an index outside the grid or a vertex with a
+ * neighbour later in the order (earlier, for minima).  With every extremum
+ * listed and budgets that no propagation reaches, the extrema paired with
+ * a saddle are those whose persistence (elder rule, in value) is at most
+ * epsilon.  The result does not depend on which propagation arrives last;
+ * with a listed vertex repeated it is unspecified.  The context keeps
+ * scratch of about 656 bytes per listed extremum (grown on demand, with a
+ * device synchronisation).  Asynchronous otherwise: kernels only, no wait.
+ * Errors as for pcrit_lts_propagate; PCRIT_E_ARG also for more than 2^30
+ * extrema, PCRIT_E_OOM if the scratch cannot be allocated. */
+int pcrit_lts_merged(pcrit_ctx *ctx, void *hip_stream, const float *field, const uint32_t *rank,
+                     int64_t nx, int64_t ny, int64_t nz, const uint32_t *extrema,
+                     int64_t n_extrema, int maxima, float epsilon, int max_visited,
+                     int max_frontier, uint8_t *status, int32_t *saddle, uint16_t *visited);
 
 #ifdef __cplusplus
 }

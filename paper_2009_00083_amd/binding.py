@@ -33,7 +33,7 @@ EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_mlp_labels", "pcrit_mlp_forward", "pcrit_mlp_backward",
             "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline",
             "pcrit_classify_batch", "pcrit_order_field", "pcrit_extrema",
-            "pcrit_lts_propagate")
+            "pcrit_lts_propagate", "pcrit_lts_merged")
 MLP_PARAMS = 6337
 MLP_INPUTS = 32
 
@@ -85,6 +85,9 @@ def _load():
     lib.pcrit_lts_propagate.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, i64, i32,
                                         ctypes.c_float, i32, i32, vp, vp, vp]
     lib.pcrit_lts_propagate.restype = i32
+    lib.pcrit_lts_merged.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, i64, i32,
+                                     ctypes.c_float, i32, i32, vp, vp, vp]
+    lib.pcrit_lts_merged.restype = i32
     lib.LEVEL_CB = ctypes.CFUNCTYPE(None, i32, i64, vp)
     lib.NULL_CB = ctypes.cast(None, lib.LEVEL_CB)
     lib.pcrit_progressive.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp,
@@ -468,6 +471,32 @@ def lts_propagate(field, rank, extrema_list, *, maxima: bool = True,
         c.handle, _stream_handle(field, stream), _ptr(field), _ptr(rank), nx, ny, nz,
         _ptr(extrema_list), n, 1 if maxima else 0, float(epsilon), int(max_visited),
         int(max_frontier), _ptr(status), _ptr(saddle), _ptr(visited)), "pcrit_lts_propagate")
+    return status[:n], saddle[:n], visited[:n]
+
+
+def lts_merged(field, rank, extrema_list, *, maxima: bool = True,
+               epsilon: float = float("inf"), max_visited: int = 16, max_frontier: int = 64,
+               ctx: Optional[Context] = None, stream=None):
+    """Merged LTS Step 1 propagations (pcrit_lts_merged): propagations that
+    meet at a saddle go on as one, led by the largest extremum; the others
+    are paired with the saddle.  ``extrema_list`` holds distinct extrema of
+    the kind asked for (as extrema() returns them).  Returns (status uint8,
+    saddle int32, visited int16) tensors, one entry per listed extremum;
+    asynchronous on the stream (the first call at a size grows the
+    context's scratch)."""
+    import torch
+    nx, ny, nz = _check_field(field)
+    c = _ctx_for(field, ctx)
+    check_buffer("rank", rank, torch.int32, field.device, numel=field.numel())
+    check_buffer("extrema", extrema_list, torch.int32, field.device)
+    n = extrema_list.numel()
+    status = torch.empty(max(n, 1), dtype=torch.uint8, device=field.device)
+    saddle = torch.empty(max(n, 1), dtype=torch.int32, device=field.device)
+    visited = torch.empty(max(n, 1), dtype=torch.int16, device=field.device)
+    _check(_load().pcrit_lts_merged(
+        c.handle, _stream_handle(field, stream), _ptr(field), _ptr(rank), nx, ny, nz,
+        _ptr(extrema_list), n, 1 if maxima else 0, float(epsilon), int(max_visited),
+        int(max_frontier), _ptr(status), _ptr(saddle), _ptr(visited)), "pcrit_lts_merged")
     return status[:n], saddle[:n], visited[:n]
 
 

@@ -125,6 +125,8 @@ struct pcrit_ctx {
   int64_t boff_bytes = 0;
   void *ord = nullptr;  // order-field sort scratch
   int64_t ord_bytes = 0;
+  void *lts = nullptr;  // merged-propagation records and saddle table
+  int64_t lts_bytes = 0;
   // second stream (default priority) on which the learned order is scored
   // while the leading levels run, and the events that fork and join it
   hipStream_t side = nullptr;
@@ -524,6 +526,7 @@ void pcrit_destroy(pcrit_ctx *c) {
   hipFree(c->tl);
   hipFree(c->boff);
   hipFree(c->ord);
+  hipFree(c->lts);
   hipFree(c->status);
   if (c->side) hipStreamDestroy(c->side);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
@@ -1370,6 +1373,29 @@ int pcrit_lts_propagate(pcrit_ctx *c, void *hip_stream, const float *field,
   return launch_lts_propagate(field, rank, nx, ny, nz, extrema, n_extrema, maxima != 0, epsilon,
                               max_visited, max_frontier, status, saddle, visited,
                               (hipStream_t)hip_stream) == hipSuccess
+             ? PCRIT_OK
+             : PCRIT_E_HIP;
+}
+int pcrit_lts_merged(pcrit_ctx *c, void *hip_stream, const float *field, const uint32_t *rank,
+                     int64_t nx, int64_t ny, int64_t nz, const uint32_t *extrema,
+                     int64_t n_extrema, int maxima, float epsilon, int max_visited,
+                     int max_frontier, uint8_t *status, int32_t *saddle, uint16_t *visited) {
+  if (!c || !field || !rank || n_extrema < 0 || n_extrema > kLtsMaxMerged ||
+      (n_extrema > 0 && (!extrema || !status || !saddle || !visited)) ||
+      misaligned(field, 4) || misaligned(rank, 4) || (extrema && misaligned(extrema, 4)) ||
+      (saddle && misaligned(saddle, 4)) || (visited && misaligned(visited, 2)) ||
+      epsilon != epsilon || max_visited < 2 || max_visited > PCRIT_LTS_MAX_VISITED ||
+      max_frontier < 14 || max_frontier > PCRIT_LTS_MAX_FRONTIER)
+    return PCRIT_E_ARG;
+  int st = check_dims(nx, ny, nz);
+  if (st) return st;
+  if (n_extrema == 0) return PCRIT_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return PCRIT_E_HIP;
+  st = ensure(&c->lts, &c->lts_bytes, (int64_t)lts_merged_scratch_bytes(n_extrema));
+  if (st) return st;
+  return launch_lts_merged(field, rank, nx, ny, nz, extrema, n_extrema, maxima != 0, epsilon,
+                           max_visited, max_frontier, status, saddle, visited, c->lts,
+                           (hipStream_t)hip_stream) == hipSuccess
              ? PCRIT_OK
              : PCRIT_E_HIP;
 }

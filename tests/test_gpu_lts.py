@@ -125,3 +125,115 @@ def test_invalid_entries_and_arguments(ctx, dev):
     empty = torch.empty(0, dtype=torch.int32, device=dev)
     st, sd, vi = pc.lts_propagate(ft, rank, empty, ctx=ctx)
     assert st.numel() == 0
+
+
+# ---------------------------------------------------------------------------
+# merged propagations (Sections 4.4 and 4.5)
+
+MERGED_CASES = [(np.inf, 16, 64), (0.0, 16, 64), (0.01, 16, 64), (0.05, 32, 128),
+                (np.inf, 2, 14), (0.02, 5, 20), (0.1, 32, 128), (np.inf, 32, 128)]
+
+
+@pytest.mark.parametrize("name,make", FIELDS)
+def test_merged_matches_oracle(ctx, dev, name, make):
+    f = make()
+    ft, rank, mn, mx = _gpu_inputs(ctx, dev, f)
+    orank, _ = oracle_order(f)
+    omn, omx = oracle_extrema(oracle.classify(f).codes)
+    assert np.array_equal(mx.cpu().numpy().view(np.uint32), omx)
+    assert np.array_equal(mn.cpu().numpy().view(np.uint32), omn)
+    merged = 0
+    for maxima in (True, False):
+        ext, oext = (mx, omx) if maxima else (mn, omn)
+        for eps, mv, mf in MERGED_CASES:
+            st, sd, vi = pc.lts_merged(ft, rank, ext, maxima=maxima, epsilon=eps,
+                                       max_visited=mv, max_frontier=mf, ctx=ctx)
+            torch.cuda.synchronize()
+            ost, osd, ovi = lts.propagate_merged(f, oext, eps, maxima, mv, mf, rank=orank)
+            what = (name, maxima, eps, mv, mf)
+            assert np.array_equal(st.cpu().numpy(), ost), what
+            assert np.array_equal(sd.cpu().numpy(), osd), what
+            assert np.array_equal(vi.cpu().numpy().astype(np.uint16), ovi), what
+            ind = lts.propagate_all(f, oext, eps, maxima, mv, mf, rank=orank)
+            merged += int(np.count_nonzero(ind[0] != ost))
+            log("merged", what, np.bincount(ost, minlength=3))
+    assert merged > 0  # some propagations went on past a saddle
+
+
+def test_merged_noise_cube(ctx, dev):
+    """A 96^3 noisy field: every maximum and minimum against the oracle, and
+    a second GPU run identical to the first (arrival order varies)."""
+    f = fieldgen.gaussian_field((96, 96, 96), 51, 6, noise=("uniform", 2e-2))
+    ft, rank, mn, mx = _gpu_inputs(ctx, dev, f)
+    orank, _ = oracle_order(f)
+    omn, omx = oracle_extrema(oracle.classify(f).codes)
+    assert np.array_equal(mx.cpu().numpy().view(np.uint32), omx)
+    for maxima, ext, oext in ((True, mx, omx), (False, mn, omn)):
+        runs = []
+        for _ in range(2):
+            st, sd, vi = pc.lts_merged(ft, rank, ext, maxima=maxima, epsilon=0.03, ctx=ctx)
+            torch.cuda.synchronize()
+            runs.append((st.cpu().numpy(), sd.cpu().numpy(), vi.cpu().numpy().astype(np.uint16)))
+        log("merged cube", maxima, len(oext))
+        ref = lts.propagate_merged(f, oext, 0.03, maxima, 16, 64, rank=orank)
+        for run in runs:
+            for a, b in zip(run, ref):
+                assert np.array_equal(a, b), maxima
+
+
+def test_merged_full_size_properties(ctx, dev):
+    """The 512^3 noise field, every maximum and minimum: two GPU runs agree;
+    a propagation that the independent one ends before its first saddle
+    (persistent or budget) ends the same way merged; every removed extremum
+    lies within epsilon of its saddle; on a sample of them the component is
+    the strict superlevel (sublevel) component of the saddle plus the
+    saddle, led by the extremum, and the saddle has a larger (smaller)
+    neighbour outside it."""
+    f = fieldgen.config_field("noisy512", device="cuda")
+    ft, rank, mn, mx = _gpu_inputs(ctx, dev, f)
+    orank = rank.cpu().numpy().view(np.uint32)
+    fl = f.ravel()
+    eps = 0.05
+    for maxima, ext in ((True, mx), (False, mn)):
+        a = [t.cpu().numpy() for t in pc.lts_merged(ft, rank, ext, maxima=maxima, epsilon=eps, ctx=ctx)]
+        b = [t.cpu().numpy() for t in pc.lts_merged(ft, rank, ext, maxima=maxima, epsilon=eps, ctx=ctx)]
+        ind = [t.cpu().numpy() for t in pc.lts_propagate(ft, rank, ext, maxima=maxima, epsilon=eps, ctx=ctx)]
+        torch.cuda.synchronize()
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+        st, sd, vi = a
+        early = ind[0] != lts.SADDLE
+        assert np.array_equal(st[early], ind[0][early]) and np.array_equal(vi[early], ind[2][early])
+        e = ext.cpu().numpy().view(np.uint32).astype(np.int64)
+        rem = np.flatnonzero(st == lts.SADDLE)
+        d = (fl[e[rem]] - fl[sd[rem]]) if maxima else (fl[sd[rem]] - fl[e[rem]])
+        assert np.all(d.astype(np.float32) <= np.float32(eps))
+        log("merged noisy512", "maxima" if maxima else "minima", len(e), np.bincount(st, minlength=3),
+            "differ from independent", int(np.count_nonzero(st != ind[0])))
+        key = orank.astype(np.int64) if maxima else orank.size - 1 - orank.astype(np.int64)
+        for j in rem[np.linspace(0, len(rem) - 1, 300).astype(np.int64)]:
+            m, s = int(e[j]), int(sd[j])
+            comp = lts.superlevel_component(f.shape, key, m, key[s] + 1)
+            assert len(comp) + 1 == vi[j] and max(key[c] for c in comp) == key[m]
+            assert any(u not in comp and key[u] > key[s] for u in lts.neighbours(f.shape, s))
+
+
+def test_merged_invalid_entries_and_arguments(ctx, dev):
+    f = fieldgen.iid_field((12, 10, 8), 41)
+    ft, rank, mn, mx = _gpu_inputs(ctx, dev, f)
+    notmax = int(mn[0])
+    bad = torch.tensor([int(mx[0]), f.size, notmax, int(mx[-1])], dtype=torch.int32, device=dev)
+    st, sd, vi = pc.lts_merged(ft, rank, bad, epsilon=0.1, ctx=ctx)
+    torch.cuda.synchronize()
+    ref = lts.propagate_merged(f, bad.cpu().numpy().view(np.uint32), 0.1)
+    assert np.array_equal(st.cpu().numpy(), ref[0]) and np.array_equal(sd.cpu().numpy(), ref[1])
+    assert st.cpu().tolist()[1:3] == [pc.LTS_INVALID, pc.LTS_INVALID]
+    for kw in ({"max_visited": 1}, {"max_visited": pc.LTS_MAX_VISITED + 1},
+               {"max_frontier": 13}, {"max_frontier": pc.LTS_MAX_FRONTIER + 1},
+               {"epsilon": float("nan")}):
+        with pytest.raises(pc.PcritError) as e:
+            pc.lts_merged(ft, rank, mx, ctx=ctx, **kw)
+        assert e.value.status == pc.E_ARG
+    empty = torch.empty(0, dtype=torch.int32, device=dev)
+    st, sd, vi = pc.lts_merged(ft, rank, empty, ctx=ctx)
+    assert st.numel() == 0
