@@ -20,8 +20,9 @@ independent fields of 33..257 samples per axis classified with shared
 launches against one call per field; "order_field": the order field
 (ranks by value, ties by index) and extremum lists of the bench field;
 "lts_step1": the superlevel / sublevel set propagation from every maximum
-and minimum of the bench field (Step 1 of the simplification, with the
-persistence test at two epsilons); the
+and minimum of the bench field (Step 1 of the simplification, each
+extremum on its own and merged at saddles, with the persistence test at two
+epsilons); the
 direct level-0 rate; per-level rates; the roofline of the dominant kernel; and the CPU
 oracle's rate on bounded samples of the same workload (all threads of this
 process's share, and one thread).
@@ -221,10 +222,13 @@ def order_measure(pc, ctx, ft, codes, reps=5):
 
 def lts_measure(pc, ctx, ft, codes, reps=5):
     """LTS Step 1 on the bench field: from every maximum and every minimum,
-    the propagation to its saddle, with the persistence test at epsilon
-    0.01 (about the noise's standard deviation) and 0.05, budget 16
-    vertices taken / 64 waiting.  Inputs (order field, extremum lists) are
-    computed first and not timed."""
+    the propagation with the persistence test at epsilon 0.01 (about the
+    noise's standard deviation) and 0.05, budget 16 vertices taken / 64
+    waiting; each extremum on its own ('max', 'min') and merged at saddles
+    ('merged_max', 'merged_min': the last arrival at a saddle goes on with
+    every arrived component).  Inputs (order field, extremum lists) are
+    computed first and not timed; the first merged call grows the scratch
+    outside the timed calls."""
     import torch
     rank, _ = pc.order_field(ft, ctx=ctx)
     mn, mx = pc.extrema(codes, ctx=ctx)
@@ -232,20 +236,24 @@ def lts_measure(pc, ctx, ft, codes, reps=5):
     out = {"maxima": int(mx.numel()), "minima": int(mn.numel()), "budget": [16, 64]}
     for eps in (0.01, 0.05):
         row = {}
-        for kind, ext, up in (("max", mx, True), ("min", mn, False)):
-            pc.lts_propagate(ft, rank, ext, maxima=up, epsilon=eps, ctx=ctx)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                st, sd, vi = pc.lts_propagate(ft, rank, ext, maxima=up, epsilon=eps, ctx=ctx)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / reps
-            cnt = np.bincount(st.cpu().numpy(), minlength=4)
-            row[kind] = {"ms": round(ms, 3), "mprop_per_s": round(ext.numel() / (ms * 1e-3) / 1e6, 1),
-                         "saddle": int(cnt[0]), "persistent": int(cnt[1]), "budget": int(cnt[2]),
-                         "mean_visited": round(float(vi.float().mean().item()), 2)}
+        for name, fn in (("", pc.lts_propagate), ("merged_", pc.lts_merged)):
+            for kind, ext, up in (("max", mx, True), ("min", mn, False)):
+                fn(ft, rank, ext, maxima=up, epsilon=eps, ctx=ctx)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    st, sd, vi = fn(ft, rank, ext, maxima=up, epsilon=eps, ctx=ctx)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+                cnt = np.bincount(st.cpu().numpy(), minlength=4)
+                row[name + kind] = {"ms": round(ms, 3),
+                                    "mprop_per_s": round(ext.numel() / (ms * 1e-3) / 1e6, 1),
+                                    "saddle": int(cnt[0]), "persistent": int(cnt[1]),
+                                    "budget": int(cnt[2]),
+                                    "mean_visited": round(float(vi.float().mean().item()), 2)}
         out[f"eps_{eps}"] = row
-    out["note"] = "one propagation per extremum, not merged at shared saddles; times include the host wait"
+    out["note"] = ("'max'/'min': one propagation per extremum; 'merged_*': propagations merged at "
+                   "saddles (saddle = paired with a saddle, i.e. removed); times include the host wait")
     return out
 
 

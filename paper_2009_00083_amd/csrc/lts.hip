@@ -104,23 +104,33 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
       st = kLtsPersistent;
       break;
     }
+    // The vertices are taken in decreasing order (a larger vertex next to
+    // the component would have made the previous one a saddle), so every
+    // vertex of the component but v is larger than v: a smaller neighbour
+    // of v is outside it, and a larger one is inside unless v is a saddle.
     const int64_t x = v % g.nx, y = (v / g.nx) % g.ny, z = v / (g.nx * g.ny);
-    bool is_saddle = false;
-    for (int k = 0; k < NB && !is_saddle; k++) {
-      const int64_t u = neighbour<DIM>(g, x, y, z, k);
-      if (u >= 0 && key(u) > kv && !in_comp((uint32_t)u)) is_saddle = true;
+    int64_t nu[NB];
+    uint32_t nk[NB];
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      nu[k] = neighbour<DIM>(g, x, y, z, k);
+      nk[k] = nu[k] >= 0 ? key(nu[k]) : 0u;
     }
+    bool is_saddle = false;
+#pragma unroll
+    for (int k = 0; k < NB; k++)
+      if (!is_saddle && nu[k] >= 0 && nk[k] > kv && !in_comp((uint32_t)nu[k])) is_saddle = true;
     if (is_saddle) {
       st = kLtsSaddle;
       sd = (int32_t)v;
       break;
     }
     if (nc >= max_visited) break;
+#pragma unroll
     for (int k = 0; k < NB; k++) {
-      const int64_t u = neighbour<DIM>(g, x, y, z, k);
-      if (u < 0 || in_comp((uint32_t)u) || waiting((uint32_t)u)) continue;
-      wv[nw] = (uint32_t)u;
-      wk[nw] = key(u);
+      if (nu[k] < 0 || nk[k] > kv || waiting((uint32_t)nu[k])) continue;
+      wv[nw] = (uint32_t)nu[k];
+      wk[nw] = nk[k];
       nw++;
     }
     if (nw > max_frontier) break;
@@ -240,13 +250,23 @@ __global__ __launch_bounds__(256) void lts_merge_kernel(
       st = kLtsPersistent;
       break;
     }
+    // taken in decreasing order (merges keep it: a merged component holds
+    // the vertices above the saddle, everything waiting lies below), so a
+    // smaller neighbour of v is outside the component
     const int64_t x = v % g.nx, y = (v / g.nx) % g.ny, z = v / (g.nx * g.ny);
-    uint32_t nh = 0, mine = 0;
+    int64_t nu[NB];
+    uint32_t nk[NB];
+#pragma unroll
     for (int k = 0; k < NB; k++) {
-      const int64_t u = neighbour<DIM>(g, x, y, z, k);
-      if (u >= 0 && key(u) > kv) {
+      nu[k] = neighbour<DIM>(g, x, y, z, k);
+      nk[k] = nu[k] >= 0 ? key(nu[k]) : 0u;
+    }
+    uint32_t nh = 0, mine = 0;
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      if (nu[k] >= 0 && nk[k] > kv) {
         nh++;
-        mine += in_comp((uint32_t)u) ? 1u : 0u;
+        mine += in_comp((uint32_t)nu[k]) ? 1u : 0u;
       }
     }
     if (mine < nh) {
@@ -336,11 +356,11 @@ __global__ __launch_bounds__(256) void lts_merge_kernel(
       st = kLtsBudget;
       break;
     }
+#pragma unroll
     for (int k = 0; k < NB; k++) {
-      const int64_t u = neighbour<DIM>(g, x, y, z, k);
-      if (u < 0 || in_comp((uint32_t)u) || waiting((uint32_t)u)) continue;
-      wv[nw] = (uint32_t)u;
-      wk[nw] = key(u);
+      if (nu[k] < 0 || nk[k] > kv || waiting((uint32_t)nu[k])) continue;
+      wv[nw] = (uint32_t)nu[k];
+      wk[nw] = nk[k];
       nw++;
     }
     if (nw > max_frontier) {
