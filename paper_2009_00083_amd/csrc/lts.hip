@@ -287,10 +287,15 @@ __global__ __launch_bounds__(256) void lts_merge_kernel(
         h = (h + 1) & tmask;
       }
       r[3] = atomicExch(&thead[h], (uint32_t)i);
-      __threadfence();
+      // release: the record, the list link and the leader's provisional
+      // status reach every XCD before the count does; acquire (last arrival
+      // only): the records parked by the others are read after the count.
+      // A full fence on every arrival would also drop the L2 lines of the
+      // field and the order field that the other propagations are reading.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const uint32_t before = atomicAdd(&tcnt[h], mine);
       if (before + mine != nh) return;  // not the last arrival
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       // the last arrival: the largest leader leads the union
       const uint32_t head = __hip_atomic_load(&thead[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int total = nc;
