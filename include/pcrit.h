@@ -509,8 +509,9 @@ int pcrit_lts_propagate(pcrit_ctx *ctx, void *hip_stream, const float *field,
  * a saddle are those whose persistence (elder rule, in value) is at most
  * epsilon.  The result does not depend on which propagation arrives last;
  * with a listed vertex repeated it is unspecified.  The context keeps
- * scratch of about 656 bytes per listed extremum (grown on demand, with a
- * device synchronisation).  Asynchronous otherwise: kernels only, no wait.
+ * scratch of about 690 bytes per listed extremum (grown on demand, with a
+ * device synchronisation).  Asynchronous otherwise: kernels only (a start
+ * kernel and max_visited merge rounds), no wait.
  * Errors as for pcrit_lts_propagate; PCRIT_E_ARG also for more than 2^30
  * extrema, PCRIT_E_OOM if the scratch cannot be allocated. */
 int pcrit_lts_merged(pcrit_ctx *ctx, void *hip_stream, const float *field, const uint32_t *rank,

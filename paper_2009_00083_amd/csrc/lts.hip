@@ -140,15 +140,31 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
   visited[i] = (uint16_t)nc;
 }
 
-// Merged propagations (Sections 4.4 and 4.5).  Scratch: one record per
-// listed extremum (its component, its waiting vertices, its leader, the
-// next record parked at the same saddle) and an open-addressing table of
-// saddles (vertex, higher neighbours taken by the arrivals so far, the last
-// record parked there).
+// Merged propagations (Sections 4.4 and 4.5), in rounds.  Scratch: one
+// record per listed extremum (a parked component, its waiting vertices, its
+// leader, the next record parked at the same saddle), an open-addressing
+// table of saddles (vertex, higher neighbours taken by the arrivals so far,
+// the last record parked there), and two queues of completed saddles.
+//
+// Round 0 runs one propagation per listed extremum up to its first stop.  A
+// propagation that stops at a saddle s parks itself, joins s's list and adds
+// the higher neighbours of s it holds to s's count; the one whose addition
+// completes the count (every higher neighbour of s taken) puts s in the
+// queue of the next round, and every propagation of the round ends there.
+// Round r + 1 merges every saddle of round r's queue: the union of the
+// parked components and waiting sets, led by the largest leader, goes on
+// from s until its next stop.  Records, statuses and queue entries of one
+// round are read only in a later kernel, so the kernel boundary orders them
+// and no fence is needed.  A component merged in round r holds at least
+// r + 2 vertices (two parked components share only s, and a propagation
+// takes a vertex before it stops again), and a union of max_visited
+// vertices stops at the budget, so max_visited rounds after round 0 finish
+// every propagation.
 constexpr int kRecWords = 4 + kLtsMaxVisited + kLtsMaxFrontier;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 // arrivals at one saddle: each holds one of its (at most 14) higher neighbours
 constexpr uint32_t kMaxArrivals = 16;
+constexpr int kRounds = kLtsMaxVisited + 1;  // counters: round 0 .. max_visited
 
 __device__ __forceinline__ uint32_t mix32(uint32_t h) {
   // integer hash "lowbias32" (C. Wellons, hash-prospector)
@@ -160,105 +176,95 @@ __device__ __forceinline__ uint32_t mix32(uint32_t h) {
   return h;
 }
 
+struct MergeArgs {
+  const float *f;
+  const uint32_t *rank;
+  Grid g;
+  const uint32_t *ext;
+  int64_t n_ext;
+  uint32_t flip;
+  float eps;
+  int max_visited, max_frontier;
+  uint8_t *status;
+  int32_t *saddle;
+  uint16_t *visited;
+  uint32_t *rec, *tkey, *tcnt, *thead, tmask;
+  uint32_t *queue[2];  // round r reads queue[r & 1]
+  uint32_t *qcount;    // qcount[r]: entries of round r's queue
+};
+
 __global__ __launch_bounds__(256) void lts_table_clear_kernel(uint32_t *tkey, uint32_t *tcnt,
-                                                              uint32_t *thead, uint32_t cap) {
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cap; j += gridDim.x * blockDim.x) {
+                                                              uint32_t *thead, uint32_t cap,
+                                                              uint32_t *qcount) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (uint32_t)kRounds + 1) qcount[t] = 0;
+  for (uint32_t j = t; j < cap; j += gridDim.x * blockDim.x) {
     tkey[j] = kNone;
     tcnt[j] = 0;
     thead[j] = kNone;
   }
 }
 
-// One thread per listed extremum.  The propagation grows as in
-// lts_propagate_kernel, led by the extremum, until it stops at a saddle s.
-// There it parks its state in its record, joins s's list and adds the
-// higher neighbours of s it holds to s's count; the thread whose addition
-// completes the count (all higher neighbours of s taken) takes over every
-// parked state, keeps the largest leader and goes on from s.  The other
-// leaders keep the saddle status written at their arrival.  No thread
-// waits for another, so every thread ends after at most max_visited takes
-// and merges.
-template <int DIM>
-__global__ __launch_bounds__(256) void lts_merge_kernel(
-    const float *f, const uint32_t *rank, Grid g, const uint32_t *ext, int64_t n_ext,
-    uint32_t flip, float eps, int max_visited, int max_frontier, uint8_t *status,
-    int32_t *saddle, uint16_t *visited, uint32_t *rec, uint32_t *tkey, uint32_t *tcnt,
-    uint32_t *thead, uint32_t tmask) {
-  constexpr int NB = DIM == 3 ? 14 : 6;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_ext) return;
-  auto key = [&](int64_t u) { return rank[u] ^ flip; };
-  const int64_t m = ext[i];
-  bool ok = m < g.n;
-  if (ok) {  // an extremum of the kind asked for: every neighbour earlier in the order
-    const int64_t x = m % g.nx, y = (m / g.nx) % g.ny, z = m / (g.nx * g.ny);
-    const uint32_t km = key(m);
-    for (int k = 0; k < NB; k++) {
-      const int64_t u = neighbour<DIM>(g, x, y, z, k);
-      if (u >= 0 && key(u) > km) ok = false;
-    }
-  }
-  if (!ok) {
-    status[i] = kLtsInvalid;
-    saddle[i] = -1;
-    visited[i] = 0;
-    return;
-  }
-  const bool maxima = flip == 0u;
+// The per-thread state of one propagation.
+struct Prop {
   uint32_t comp[kLtsMaxVisited];
   uint32_t wv[kLtsMaxFrontier + 14], wk[kLtsMaxFrontier + 14];
-  int nc = 1, nw = 0;
-  comp[0] = (uint32_t)m;
-  uint32_t lead = (uint32_t)i;
-  float fl = f[m];
-  auto in_comp = [&](uint32_t u) {
+  int nc, nw;
+  uint32_t lead;
+  float fl;
+  __device__ bool in_comp(uint32_t u) const {
     for (int j = 0; j < nc; j++)
       if (comp[j] == u) return true;
     return false;
-  };
-  auto waiting = [&](uint32_t u) {
+  }
+  __device__ bool waiting(uint32_t u) const {
     for (int j = 0; j < nw; j++)
       if (wv[j] == u) return true;
     return false;
-  };
-  {
-    const int64_t x = m % g.nx, y = (m / g.nx) % g.ny, z = m / (g.nx * g.ny);
-    for (int k = 0; k < NB; k++) {
-      const int64_t u = neighbour<DIM>(g, x, y, z, k);
-      if (u < 0) continue;
-      wv[nw] = (uint32_t)u;
-      wk[nw] = key(u);
-      nw++;
-    }
   }
-  uint8_t st;
+};
+
+__device__ __forceinline__ void finish(const MergeArgs &a, uint32_t lead, uint8_t st, int nc) {
+  a.status[lead] = st;
+  a.saddle[lead] = -1;
+  a.visited[lead] = (uint16_t)nc;
+}
+
+// Run propagation p (record `own`) in round `round` until it stops: the
+// leader's final status, or an arrival at a saddle (parked, and the saddle
+// queued for the next round when this arrival completes its count).
+template <int DIM>
+__device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
+  constexpr int NB = DIM == 3 ? 14 : 6;
+  const bool maxima = a.flip == 0u;
+  auto key = [&](int64_t u) { return a.rank[u] ^ a.flip; };
   for (;;) {
-    if (nw == 0) {  // the whole grid taken: nothing ends this extremum
-      st = kLtsPersistent;
-      break;
+    if (p.nw == 0) {  // the whole grid taken: nothing ends this extremum
+      finish(a, p.lead, kLtsPersistent, p.nc);
+      return;
     }
     int b = 0;
-    for (int j = 1; j < nw; j++)
-      if (wk[j] > wk[b]) b = j;
-    const uint32_t v = wv[b], kv = wk[b];
-    wv[b] = wv[nw - 1];
-    wk[b] = wk[nw - 1];
-    nw--;
-    comp[nc++] = v;
-    const float d = maxima ? fl - f[v] : f[v] - fl;
-    if (d > eps) {
-      st = kLtsPersistent;
-      break;
+    for (int j = 1; j < p.nw; j++)
+      if (p.wk[j] > p.wk[b]) b = j;
+    const uint32_t v = p.wv[b], kv = p.wk[b];
+    p.wv[b] = p.wv[p.nw - 1];
+    p.wk[b] = p.wk[p.nw - 1];
+    p.nw--;
+    p.comp[p.nc++] = v;
+    const float d = maxima ? p.fl - a.f[v] : a.f[v] - p.fl;
+    if (d > a.eps) {
+      finish(a, p.lead, kLtsPersistent, p.nc);
+      return;
     }
-    // taken in decreasing order (merges keep it: a merged component holds
-    // the vertices above the saddle, everything waiting lies below), so a
-    // smaller neighbour of v is outside the component
-    const int64_t x = v % g.nx, y = (v / g.nx) % g.ny, z = v / (g.nx * g.ny);
+    // taken in decreasing order (a merged component holds the vertices above
+    // its saddle, everything waiting lies below), so a smaller neighbour of
+    // v is outside the component
+    const int64_t x = v % a.g.nx, y = (v / a.g.nx) % a.g.ny, z = v / (a.g.nx * a.g.ny);
     int64_t nu[NB];
     uint32_t nk[NB];
 #pragma unroll
     for (int k = 0; k < NB; k++) {
-      nu[k] = neighbour<DIM>(g, x, y, z, k);
+      nu[k] = neighbour<DIM>(a.g, x, y, z, k);
       nk[k] = nu[k] >= 0 ? key(nu[k]) : 0u;
     }
     uint32_t nh = 0, mine = 0;
@@ -266,116 +272,159 @@ __global__ __launch_bounds__(256) void lts_merge_kernel(
     for (int k = 0; k < NB; k++) {
       if (nu[k] >= 0 && nk[k] > kv) {
         nh++;
-        mine += in_comp((uint32_t)nu[k]) ? 1u : 0u;
+        mine += p.in_comp((uint32_t)nu[k]) ? 1u : 0u;
       }
     }
-    if (mine < nh) {
-      // arrival at the saddle v: park, join v's list, add to its count
-      uint32_t *r = rec + (size_t)i * kRecWords;
-      r[0] = (uint32_t)nc;
-      r[1] = (uint32_t)nw;
-      r[2] = lead;
-      for (int j = 0; j < nc; j++) r[4 + j] = comp[j];
-      for (int j = 0; j < nw; j++) r[4 + kLtsMaxVisited + j] = wv[j];
-      status[lead] = kLtsSaddle;
-      saddle[lead] = (int32_t)v;
-      visited[lead] = (uint16_t)nc;
-      uint32_t h = mix32(v) & tmask;
-      for (uint32_t probe = 0; probe <= tmask; probe++) {  // at most half full: ends
-        const uint32_t k = atomicCAS(&tkey[h], kNone, v);
+    if (mine < nh) {  // arrival at the saddle v
+      uint32_t *r = a.rec + (size_t)own * kRecWords;
+      r[0] = (uint32_t)p.nc;
+      r[1] = (uint32_t)p.nw;
+      r[2] = p.lead;
+      for (int j = 0; j < p.nc; j++) r[4 + j] = p.comp[j];
+      for (int j = 0; j < p.nw; j++) r[4 + kLtsMaxVisited + j] = p.wv[j];
+      a.status[p.lead] = kLtsSaddle;  // final unless a merge picks this leader
+      a.saddle[p.lead] = (int32_t)v;
+      a.visited[p.lead] = (uint16_t)p.nc;
+      uint32_t h = mix32(v) & a.tmask;
+      for (uint32_t probe = 0; probe <= a.tmask; probe++) {  // at most half full: ends
+        const uint32_t k = atomicCAS(&a.tkey[h], kNone, v);
         if (k == kNone || k == v) break;
-        h = (h + 1) & tmask;
+        h = (h + 1) & a.tmask;
       }
-      r[3] = atomicExch(&thead[h], (uint32_t)i);
-      // release: the record, the list link and the leader's provisional
-      // status reach every XCD before the count does; acquire (last arrival
-      // only): the records parked by the others are read after the count.
-      // A full fence on every arrival would also drop the L2 lines of the
-      // field and the order field that the other propagations are reading.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const uint32_t before = atomicAdd(&tcnt[h], mine);
-      if (before + mine != nh) return;  // not the last arrival
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      // the last arrival: the largest leader leads the union
-      const uint32_t head = __hip_atomic_load(&thead[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int total = nc;
-      uint32_t best = lead, bkey = key(ext[lead]);
-      // every record in the list was written by an arrival of this launch:
-      // index, counts and leader are in range (the checks only keep a
-      // broken invariant from reading past the buffers)
-      for (uint32_t q = head, step = 0; q < (uint32_t)n_ext && step < kMaxArrivals;
-           q = rec[(size_t)q * kRecWords + 3], step++) {
-        if (q == (uint32_t)i) continue;
-        const uint32_t *o = rec + (size_t)q * kRecWords;
-        total += (int)min(o[0], (uint32_t)kLtsMaxVisited) - 1;  // v is in every parked component
-        const uint32_t ol = min(o[2], (uint32_t)(n_ext - 1));
-        const uint32_t kl = key(ext[ol]);
-        if (kl > bkey) {
-          bkey = kl;
-          best = ol;
-        }
+      r[3] = atomicExch(&a.thead[h], own);
+      if (atomicAdd(&a.tcnt[h], mine) + mine == nh && round + 1 < kRounds) {
+        const uint32_t q = atomicAdd(&a.qcount[round + 1], 1u);
+        if (q < (uint32_t)a.n_ext) a.queue[(round + 1) & 1][q] = h;
       }
-      lead = best;
-      fl = f[ext[best]];
-      if (total >= max_visited) {
-        nc = total;
-        st = kLtsBudget;
-        break;
-      }
-      for (uint32_t q = head, step = 0; q < (uint32_t)n_ext && step < kMaxArrivals;
-           q = rec[(size_t)q * kRecWords + 3], step++) {
-        if (q == (uint32_t)i) continue;
-        const uint32_t *o = rec + (size_t)q * kRecWords;
-        const int on = (int)min(o[0], (uint32_t)kLtsMaxVisited);
-        for (int j = 0; j < on && nc < kLtsMaxVisited; j++)
-          if (o[4 + j] != v) comp[nc++] = o[4 + j];
-      }
-      bool over = false;
-      for (uint32_t q = head, step = 0; q < (uint32_t)n_ext && step < kMaxArrivals && !over;
-           q = rec[(size_t)q * kRecWords + 3], step++) {
-        if (q == (uint32_t)i) continue;
-        const uint32_t *o = rec + (size_t)q * kRecWords;
-        const int ow = (int)min(o[1], (uint32_t)kLtsMaxFrontier);
-        for (int j = 0; j < ow && !over; j++) {
-          const uint32_t u = o[4 + kLtsMaxVisited + j];
-          if (u >= g.n || in_comp(u) || waiting(u)) continue;
-          wv[nw] = u;
-          wk[nw] = key(u);
-          over = ++nw > max_frontier;
-        }
-      }
-      for (int k = 0; k < NB && !over; k++) {
-        const int64_t u = neighbour<DIM>(g, x, y, z, k);
-        if (u < 0 || in_comp((uint32_t)u) || waiting((uint32_t)u)) continue;
-        wv[nw] = (uint32_t)u;
-        wk[nw] = key(u);
-        over = ++nw > max_frontier;
-      }
-      if (over) {
-        st = kLtsBudget;
-        break;
-      }
-      continue;
+      return;
     }
-    if (nc >= max_visited) {
-      st = kLtsBudget;
-      break;
+    if (p.nc >= a.max_visited) {
+      finish(a, p.lead, kLtsBudget, p.nc);
+      return;
     }
 #pragma unroll
     for (int k = 0; k < NB; k++) {
-      if (nu[k] < 0 || nk[k] > kv || waiting((uint32_t)nu[k])) continue;
-      wv[nw] = (uint32_t)nu[k];
-      wk[nw] = nk[k];
-      nw++;
+      if (nu[k] < 0 || nk[k] > kv || p.waiting((uint32_t)nu[k])) continue;
+      p.wv[p.nw] = (uint32_t)nu[k];
+      p.wk[p.nw] = nk[k];
+      p.nw++;
     }
-    if (nw > max_frontier) {
-      st = kLtsBudget;
-      break;
+    if (p.nw > a.max_frontier) {
+      finish(a, p.lead, kLtsBudget, p.nc);
+      return;
     }
   }
-  status[lead] = st;
-  saddle[lead] = -1;
-  visited[lead] = (uint16_t)nc;
+}
+
+// Round 0: one thread per listed extremum.
+template <int DIM>
+__global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
+  constexpr int NB = DIM == 3 ? 14 : 6;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_ext) return;
+  auto key = [&](int64_t u) { return a.rank[u] ^ a.flip; };
+  const int64_t m = a.ext[i];
+  bool ok = m < a.g.n;
+  const int64_t x = m % a.g.nx, y = (m / a.g.nx) % a.g.ny, z = m / (a.g.nx * a.g.ny);
+  if (ok) {  // an extremum of the kind asked for: every neighbour earlier in the order
+    const uint32_t km = key(m);
+    for (int k = 0; k < NB; k++) {
+      const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
+      if (u >= 0 && key(u) > km) ok = false;
+    }
+  }
+  if (!ok) {
+    a.status[i] = kLtsInvalid;
+    a.saddle[i] = -1;
+    a.visited[i] = 0;
+    return;
+  }
+  Prop p;
+  p.nc = 1;
+  p.nw = 0;
+  p.comp[0] = (uint32_t)m;
+  p.lead = (uint32_t)i;
+  p.fl = a.f[m];
+  for (int k = 0; k < NB; k++) {
+    const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
+    if (u < 0) continue;
+    p.wv[p.nw] = (uint32_t)u;
+    p.wk[p.nw] = key(u);
+    p.nw++;
+  }
+  advance<DIM>(a, 0, (uint32_t)i, p);
+}
+
+// Round r >= 1: one thread per saddle completed in round r - 1.
+template <int DIM>
+__global__ __launch_bounds__(256) void lts_merge_round_kernel(MergeArgs a, int round) {
+  constexpr int NB = DIM == 3 ? 14 : 6;
+  const uint32_t cnt = min(a.qcount[round], (uint32_t)a.n_ext);
+  auto key = [&](int64_t u) { return a.rank[u] ^ a.flip; };
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const uint32_t h = min(a.queue[round & 1][t], a.tmask);
+    const uint32_t v = a.tkey[h], head = a.thead[h];
+    if (v >= a.g.n || head >= (uint32_t)a.n_ext) continue;  // never: queued slots hold both
+    // every record in the list was parked in an earlier round: index,
+    // counts and leader are in range (the clamps only keep a broken
+    // invariant from reading past the buffers)
+    Prop p;
+    int total = 1;
+    uint32_t best = kNone, bkey = 0;
+    for (uint32_t q = head, step = 0; q < (uint32_t)a.n_ext && step < kMaxArrivals;
+         q = a.rec[(size_t)q * kRecWords + 3], step++) {
+      const uint32_t *o = a.rec + (size_t)q * kRecWords;
+      total += (int)min(o[0], (uint32_t)kLtsMaxVisited) - 1;  // v is in every parked component
+      const uint32_t ol = min(o[2], (uint32_t)(a.n_ext - 1));
+      const uint32_t kl = key(a.ext[ol]);
+      if (best == kNone || kl > bkey) {
+        bkey = kl;
+        best = ol;
+      }
+    }
+    p.lead = best;
+    p.fl = a.f[a.ext[best]];
+    if (total >= a.max_visited) {
+      finish(a, best, kLtsBudget, total);
+      continue;
+    }
+    p.nc = 0;
+    p.nw = 0;
+    p.comp[p.nc++] = v;
+    for (uint32_t q = head, step = 0; q < (uint32_t)a.n_ext && step < kMaxArrivals;
+         q = a.rec[(size_t)q * kRecWords + 3], step++) {
+      const uint32_t *o = a.rec + (size_t)q * kRecWords;
+      const int on = (int)min(o[0], (uint32_t)kLtsMaxVisited);
+      for (int j = 0; j < on && p.nc < kLtsMaxVisited; j++)
+        if (o[4 + j] != v) p.comp[p.nc++] = o[4 + j];
+    }
+    bool over = false;
+    for (uint32_t q = head, step = 0; q < (uint32_t)a.n_ext && step < kMaxArrivals && !over;
+         q = a.rec[(size_t)q * kRecWords + 3], step++) {
+      const uint32_t *o = a.rec + (size_t)q * kRecWords;
+      const int ow = (int)min(o[1], (uint32_t)kLtsMaxFrontier);
+      for (int j = 0; j < ow && !over; j++) {
+        const uint32_t u = o[4 + kLtsMaxVisited + j];
+        if (u >= a.g.n || p.in_comp(u) || p.waiting(u)) continue;
+        p.wv[p.nw] = u;
+        p.wk[p.nw] = key(u);
+        over = ++p.nw > a.max_frontier;
+      }
+    }
+    const int64_t x = v % a.g.nx, y = (v / a.g.nx) % a.g.ny, z = v / (a.g.nx * a.g.ny);
+    for (int k = 0; k < NB && !over; k++) {  // the saddle's own neighbours
+      const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
+      if (u < 0 || p.in_comp((uint32_t)u) || p.waiting((uint32_t)u)) continue;
+      p.wv[p.nw] = (uint32_t)u;
+      p.wk[p.nw] = key(u);
+      over = ++p.nw > a.max_frontier;
+    }
+    if (over) {
+      finish(a, best, kLtsBudget, p.nc);
+      continue;
+    }
+    advance<DIM>(a, round, head, p);  // the merged propagation owns the head record
+  }
 }
 
 uint32_t table_cap(int64_t n_ext) {
@@ -387,7 +436,8 @@ uint32_t table_cap(int64_t n_ext) {
 }  // namespace
 
 size_t lts_merged_scratch_bytes(int64_t n_ext) {
-  return (size_t)n_ext * kRecWords * 4 + (size_t)table_cap(n_ext) * 12;
+  return (size_t)n_ext * kRecWords * 4 + (size_t)table_cap(n_ext) * 12 + (size_t)n_ext * 8 +
+         (kRounds + 1) * 4;
 }
 
 hipError_t launch_lts_merged(const float *f, const uint32_t *rank, int64_t nx, int64_t ny,
@@ -398,22 +448,43 @@ hipError_t launch_lts_merged(const float *f, const uint32_t *rank, int64_t nx, i
   if (max_visited < 2 || max_visited > kLtsMaxVisited || max_frontier < 14 ||
       max_frontier > kLtsMaxFrontier || n_ext > kLtsMaxMerged)
     return hipErrorInvalidValue;
-  const Grid g{nx, ny, nz, nx * ny * nz};
+  MergeArgs a;
+  a.f = f;
+  a.rank = rank;
+  a.g = Grid{nx, ny, nz, nx * ny * nz};
+  a.ext = ext;
+  a.n_ext = n_ext;
+  a.flip = maxima ? 0u : 0xFFFFFFFFu;
+  a.eps = eps;
+  a.max_visited = max_visited;
+  a.max_frontier = max_frontier;
+  a.status = status;
+  a.saddle = saddle;
+  a.visited = visited;
   const uint32_t cap = table_cap(n_ext);
-  uint32_t *rec = (uint32_t *)scratch;
-  uint32_t *tkey = rec + (size_t)n_ext * kRecWords, *tcnt = tkey + cap, *thead = tcnt + cap;
-  hipLaunchKernelGGL(lts_table_clear_kernel, dim3(std::min<uint32_t>((cap + 255) / 256, 2048)), dim3(256),
-                     0, st, tkey, tcnt, thead, cap);
+  a.rec = (uint32_t *)scratch;
+  a.tkey = a.rec + (size_t)n_ext * kRecWords;
+  a.tcnt = a.tkey + cap;
+  a.thead = a.tcnt + cap;
+  a.tmask = cap - 1;
+  a.queue[0] = a.thead + cap;
+  a.queue[1] = a.queue[0] + n_ext;
+  a.qcount = a.queue[1] + n_ext;
+  hipLaunchKernelGGL(lts_table_clear_kernel, dim3(std::min<uint32_t>((cap + 255) / 256, 2048)),
+                     dim3(256), 0, st, a.tkey, a.tcnt, a.thead, cap, a.qcount);
   const dim3 grid((unsigned)((n_ext + 255) / 256)), block(256);
-  const uint32_t flip = maxima ? 0u : 0xFFFFFFFFu;
-  if (nz > 1)
-    hipLaunchKernelGGL(lts_merge_kernel<3>, grid, block, 0, st, f, rank, g, ext, n_ext, flip, eps,
-                       max_visited, max_frontier, status, saddle, visited, rec, tkey, tcnt, thead,
-                       cap - 1);
-  else
-    hipLaunchKernelGGL(lts_merge_kernel<2>, grid, block, 0, st, f, rank, g, ext, n_ext, flip, eps,
-                       max_visited, max_frontier, status, saddle, visited, rec, tkey, tcnt, thead,
-                       cap - 1);
+  // rounds: a fixed grid striding over the round's queue (at most one entry
+  // per parked propagation); empty rounds end at once
+  const dim3 rgrid((unsigned)std::min<int64_t>((n_ext + 255) / 256, 2048));
+  if (nz > 1) {
+    hipLaunchKernelGGL(lts_merge_start_kernel<3>, grid, block, 0, st, a);
+    for (int r = 1; r <= max_visited; r++)
+      hipLaunchKernelGGL(lts_merge_round_kernel<3>, rgrid, block, 0, st, a, r);
+  } else {
+    hipLaunchKernelGGL(lts_merge_start_kernel<2>, grid, block, 0, st, a);
+    for (int r = 1; r <= max_visited; r++)
+      hipLaunchKernelGGL(lts_merge_round_kernel<2>, rgrid, block, 0, st, a, r);
+  }
   return hipGetLastError();
 }
 
