@@ -31,18 +31,29 @@ __constant__ int8_t kNb3[14][3] = {{1, 0, 0},   {0, 1, 0},   {1, 1, 0},   {0, 0,
                                    {0, 0, -1},  {-1, 0, -1}, {0, -1, -1}, {-1, -1, -1}};
 __constant__ int8_t kNb2[6][3] = {{1, 0, 0}, {0, 1, 0}, {1, 1, 0}, {-1, 0, 0}, {0, -1, 0}, {-1, -1, 0}};
 
+// Grids hold fewer than 2^32 vertices, so indices and coordinates are
+// 32-bit (a 64-bit division is a long emulated sequence on the GPU).
 struct Grid {
-  int64_t nx, ny, nz, n;
+  uint32_t nx, ny, nz, n;
 };
 
-// Neighbour k of vertex v (x, y, z), or -1 outside the grid.
+__device__ __forceinline__ void coords(const Grid &g, uint32_t v, uint32_t &x, uint32_t &y,
+                                       uint32_t &z) {
+  const uint32_t q = v / g.nx;
+  x = v - q * g.nx;
+  z = q / g.ny;
+  y = q - z * g.ny;
+}
+
+// Neighbour k of vertex (x, y, z), or -1 outside the grid (a coordinate
+// below 0 wraps past the grid's extent).
 template <int DIM>
-__device__ __forceinline__ int64_t neighbour(const Grid &g, int64_t x, int64_t y, int64_t z,
+__device__ __forceinline__ int64_t neighbour(const Grid &g, uint32_t x, uint32_t y, uint32_t z,
                                              int k) {
   const int8_t *o = DIM == 3 ? kNb3[k] : kNb2[k];
-  const int64_t a = x + o[0], b = y + o[1], c = z + o[2];
-  if (a < 0 || a >= g.nx || b < 0 || b >= g.ny || c < 0 || c >= g.nz) return -1;
-  return (c * g.ny + b) * g.nx + a;
+  const uint32_t a = x + o[0], b = y + o[1], c = z + o[2];
+  if (a >= g.nx || b >= g.ny || c >= g.nz) return -1;
+  return (int64_t)((c * g.ny + b) * g.nx + a);
 }
 
 template <int DIM>
@@ -78,7 +89,8 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
     return false;
   };
   {
-    const int64_t x = m % g.nx, y = (m / g.nx) % g.ny, z = m / (g.nx * g.ny);
+    uint32_t x, y, z;
+    coords(g, (uint32_t)m, x, y, z);
     for (int k = 0; k < NB; k++) {
       const int64_t u = neighbour<DIM>(g, x, y, z, k);
       if (u < 0) continue;
@@ -108,7 +120,8 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
     // the component would have made the previous one a saddle), so every
     // vertex of the component but v is larger than v: a smaller neighbour
     // of v is outside it, and a larger one is inside unless v is a saddle.
-    const int64_t x = v % g.nx, y = (v / g.nx) % g.ny, z = v / (g.nx * g.ny);
+    uint32_t x, y, z;
+    coords(g, (uint32_t)v, x, y, z);
     int64_t nu[NB];
     uint32_t nk[NB];
 #pragma unroll
@@ -259,7 +272,8 @@ __device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
     // taken in decreasing order (a merged component holds the vertices above
     // its saddle, everything waiting lies below), so a smaller neighbour of
     // v is outside the component
-    const int64_t x = v % a.g.nx, y = (v / a.g.nx) % a.g.ny, z = v / (a.g.nx * a.g.ny);
+    uint32_t x, y, z;
+    coords(a.g, (uint32_t)v, x, y, z);
     int64_t nu[NB];
     uint32_t nk[NB];
 #pragma unroll
@@ -325,7 +339,8 @@ __global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
   auto key = [&](int64_t u) { return a.rank[u] ^ a.flip; };
   const int64_t m = a.ext[i];
   bool ok = m < a.g.n;
-  const int64_t x = m % a.g.nx, y = (m / a.g.nx) % a.g.ny, z = m / (a.g.nx * a.g.ny);
+  uint32_t x, y, z;
+    coords(a.g, (uint32_t)m, x, y, z);
   if (ok) {  // an extremum of the kind asked for: every neighbour earlier in the order
     const uint32_t km = key(m);
     for (int k = 0; k < NB; k++) {
@@ -411,7 +426,8 @@ __global__ __launch_bounds__(256) void lts_merge_round_kernel(MergeArgs a, int r
         over = ++p.nw > a.max_frontier;
       }
     }
-    const int64_t x = v % a.g.nx, y = (v / a.g.nx) % a.g.ny, z = v / (a.g.nx * a.g.ny);
+    uint32_t x, y, z;
+    coords(a.g, (uint32_t)v, x, y, z);
     for (int k = 0; k < NB && !over; k++) {  // the saddle's own neighbours
       const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
       if (u < 0 || p.in_comp((uint32_t)u) || p.waiting((uint32_t)u)) continue;
@@ -451,7 +467,7 @@ hipError_t launch_lts_merged(const float *f, const uint32_t *rank, int64_t nx, i
   MergeArgs a;
   a.f = f;
   a.rank = rank;
-  a.g = Grid{nx, ny, nz, nx * ny * nz};
+  a.g = Grid{(uint32_t)nx, (uint32_t)ny, (uint32_t)nz, (uint32_t)(nx * ny * nz)};
   a.ext = ext;
   a.n_ext = n_ext;
   a.flip = maxima ? 0u : 0xFFFFFFFFu;
@@ -496,7 +512,7 @@ hipError_t launch_lts_propagate(const float *f, const uint32_t *rank, int64_t nx
   if (max_visited < 2 || max_visited > kLtsMaxVisited || max_frontier < 14 ||
       max_frontier > kLtsMaxFrontier)
     return hipErrorInvalidValue;
-  const Grid g{nx, ny, nz, nx * ny * nz};
+  const Grid g{(uint32_t)nx, (uint32_t)ny, (uint32_t)nz, (uint32_t)(nx * ny * nz)};
   const dim3 grid((unsigned)((n_ext + 255) / 256)), block(256);
   const uint32_t flip = maxima ? 0u : 0xFFFFFFFFu;
   if (nz > 1)
