@@ -339,13 +339,20 @@ __global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
   auto key = [&](int64_t u) { return a.rank[u] ^ a.flip; };
   const int64_t m = a.ext[i];
   bool ok = m < a.g.n;
-  uint32_t x, y, z;
+  Prop p;
+  p.nc = 1;
+  p.nw = 0;
+  if (ok) {  // the neighbours wait; an extremum of the kind asked for comes after all of them
+    uint32_t x, y, z;
     coords(a.g, (uint32_t)m, x, y, z);
-  if (ok) {  // an extremum of the kind asked for: every neighbour earlier in the order
     const uint32_t km = key(m);
     for (int k = 0; k < NB; k++) {
       const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
-      if (u >= 0 && key(u) > km) ok = false;
+      if (u < 0) continue;
+      p.wv[p.nw] = (uint32_t)u;
+      p.wk[p.nw] = key(u);
+      ok = ok && p.wk[p.nw] < km;
+      p.nw++;
     }
   }
   if (!ok) {
@@ -354,19 +361,9 @@ __global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
     a.visited[i] = 0;
     return;
   }
-  Prop p;
-  p.nc = 1;
-  p.nw = 0;
   p.comp[0] = (uint32_t)m;
   p.lead = (uint32_t)i;
   p.fl = a.f[m];
-  for (int k = 0; k < NB; k++) {
-    const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
-    if (u < 0) continue;
-    p.wv[p.nw] = (uint32_t)u;
-    p.wk[p.nw] = key(u);
-    p.nw++;
-  }
   advance<DIM>(a, 0, (uint32_t)i, p);
 }
 
@@ -489,9 +486,9 @@ hipError_t launch_lts_merged(const float *f, const uint32_t *rank, int64_t nx, i
   hipLaunchKernelGGL(lts_table_clear_kernel, dim3(std::min<uint32_t>((cap + 255) / 256, 2048)),
                      dim3(256), 0, st, a.tkey, a.tcnt, a.thead, cap, a.qcount);
   const dim3 grid((unsigned)((n_ext + 255) / 256)), block(256);
-  // rounds: a fixed grid striding over the round's queue (at most one entry
-  // per parked propagation); empty rounds end at once
-  const dim3 rgrid((unsigned)std::min<int64_t>((n_ext + 255) / 256, 2048));
+  // rounds: one thread per possible queue entry (at most one per parked
+  // propagation), striding if fewer; empty rounds end at once
+  const dim3 rgrid = grid;
   if (nz > 1) {
     hipLaunchKernelGGL(lts_merge_start_kernel<3>, grid, block, 0, st, a);
     for (int r = 1; r <= max_visited; r++)
