@@ -125,7 +125,8 @@ def batch_measure(pc, ctx, dev, reps=10):
     per field: 200 3D fields, every axis drawn from U{33..257} (seed 5),
     each 8 Gaussians (the small-field recipe without noise), resident on the
     GPU; every way enqueued back to back with device-side counts; the
-    batched call also as a replayed HIP graph."""
+    batched call also as a replayed HIP graph, and with the launch
+    configuration the autotuner picks for this batch ('tuned')."""
     import torch
     import fieldgen
     rng = np.random.default_rng(5)
@@ -185,6 +186,29 @@ def batch_measure(pc, ctx, dev, reps=10):
         ms = (time.perf_counter() - t0) * 1e3 / reps
         out[name + "_ms"] = round(ms, 3)
         out[name + "_gvps"] = round(nv / (ms * 1e-3) / 1e9, 2)
+    # the launch configuration tuned on this batch (a context of its own):
+    # every candidate's time, the choice, and the batched call with it
+    tctx = pc.Context(0)
+    choice, table, tcodes, tcrit, _ = pc.batch_autotune(ts, ctx=tctx, reps=3)
+    torch.cuda.synchronize()
+    n = int(ref.offsets[-1])
+    assert torch.equal(tcrit[:n], ref.crit[:n])
+    tcrit = tcodes = None
+
+    def tuned():
+        pc.classify_batch(ts, ctx=tctx, codes=codes, crit=crit, offsets_dev=offs)
+
+    tuned()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tuned()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    assert torch.equal(offs.cpu(), torch.from_numpy(ref.offsets))
+    out["tuned"] = {"group": choice[0], "want_tiles": choice[1], "ms": round(ms, 3),
+                    "gvps": round(nv / (ms * 1e-3) / 1e9, 2),
+                    "candidates_ms": {f"{g}x{w}": round(v, 3) for (g, w), v in table.items()}}
     out.update({"fields": BATCH_FIELDS, "axis": list(BATCH_AXIS), "vertices": int(nv),
                 "critical": int(ref.offsets[-1]),
                 "speedup": round(out["per_field_ms"] / out["batched_ms"], 2)})

@@ -424,6 +424,35 @@ int pcrit_classify_batch(pcrit_ctx *ctx, void *hip_stream, int n_fields,
                          uint8_t *crit_codes, int64_t crit_capacity,
                          int64_t *offsets_host, int64_t *offsets_dev);
 
+/* Batch launch configuration (per context): `group` fields share one
+ * classification launch and one compaction launch (1 ..
+ * PCRIT_BATCH_GROUP_MAX; 0 = the default, 16), and each field's tiles are
+ * as deep as still gives `want_tiles` wave tiles per field (64 .. 2^20;
+ * 0 = the default, 512).  Results do not depend on it; only the time
+ * does.  PCRIT_E_ARG for values out of range. */
+#define PCRIT_BATCH_GROUP_MAX 16
+int pcrit_set_batch_config(pcrit_ctx *ctx, int group, int64_t want_tiles);
+int pcrit_get_batch_config(pcrit_ctx *ctx, int *group, int64_t *want_tiles);
+
+/* Autotuner of the batch configuration: times pcrit_classify_batch on the
+ * caller's fields and buffers (arguments as there) for each of
+ * PCRIT_BATCH_TUNE_CANDIDATES configurations, group in {8, 16} (outer)
+ * times want_tiles in {128, 256, 512, 1024, 2048, 4096} (inner), each after one
+ * untimed call, over `reps` calls (1 .. 100) between two HIP events on the
+ * stream, and keeps the fastest in the context for later batch calls.
+ * times_ms_host (NULL or PCRIT_BATCH_TUNE_CANDIDATES doubles) receives the
+ * time per call of each candidate in that order; group_out and want_out
+ * (NULL or one each) the choice.  A first call with the context's
+ * configuration checks the batch (its errors are returned, the
+ * configuration is then unchanged); a last call with the chosen one leaves
+ * the batch's lists and codes in the caller's buffers.  The call
+ * waits for the stream; not for graph capture (scratch may grow). */
+#define PCRIT_BATCH_TUNE_CANDIDATES 12
+int pcrit_batch_autotune(pcrit_ctx *ctx, void *hip_stream, int n_fields,
+                         const pcrit_batch_field *fields_host, uint32_t *crit,
+                         uint8_t *crit_codes, int64_t crit_capacity, int reps,
+                         double *times_ms_host, int *group_out, int64_t *want_out);
+
 /* ------------------------------------------------------------------------
  * Order field and extremum lists (the
  * inputs of the paper's simplification).

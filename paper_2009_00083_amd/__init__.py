@@ -8,7 +8,7 @@ streams.  There is no CPU fallback: if the library is missing, every call
 raises.
 """
 from .binding import (  # noqa: F401
-    PcritError, Context, classify, classify_noalloc, classify_batch, BatchResult, order_field, extrema, lts_propagate, lts_merged, progressive, progressive_async, max_level, level_dims,
+    PcritError, Context, classify, classify_noalloc, classify_batch, BatchResult, order_field, extrema, lts_propagate, lts_merged, batch_autotune, progressive, progressive_async, max_level, level_dims,
     link_table, preview_f1, preview_f1_levels, library_path, decode, is_critical, point_type,
     region_count, mlp_feature_level, mlp_features, mlp_labels, mlp_forward, mlp_backward,
     mlp_adam, progressive_timeline, MLP_PARAMS, MLP_INPUTS,

@@ -33,7 +33,8 @@ EXPORTED = ("pcrit_create", "pcrit_destroy", "pcrit_strerror",
             "pcrit_mlp_labels", "pcrit_mlp_forward", "pcrit_mlp_backward",
             "pcrit_mlp_adam", "pcrit_region_count", "pcrit_progressive_timeline",
             "pcrit_classify_batch", "pcrit_order_field", "pcrit_extrema",
-            "pcrit_lts_propagate", "pcrit_lts_merged")
+            "pcrit_lts_propagate", "pcrit_lts_merged", "pcrit_set_batch_config",
+            "pcrit_get_batch_config", "pcrit_batch_autotune")
 MLP_PARAMS = 6337
 MLP_INPUTS = 32
 
@@ -97,6 +98,12 @@ def _load():
     lib.pcrit_progressive_async.restype = i32
     lib.pcrit_set_kernel_timing.argtypes = [vp, ctypes.c_uint64]
     lib.pcrit_set_kernel_timing.restype = i32
+    lib.pcrit_set_batch_config.argtypes = [vp, i32, i64]
+    lib.pcrit_set_batch_config.restype = i32
+    lib.pcrit_get_batch_config.argtypes = [vp, vp, vp]
+    lib.pcrit_get_batch_config.restype = i32
+    lib.pcrit_batch_autotune.argtypes = [vp, vp, i32, vp, vp, vp, i64, i32, vp, vp, vp]
+    lib.pcrit_batch_autotune.restype = i32
     lib.pcrit_kernel_ms.argtypes = [vp, vp, vp, i32]
     lib.pcrit_kernel_ms.restype = i32
     lib.pcrit_preview_f1.argtypes = [i64, i64, i64, i32, vp, vp, i64, vp, vp,
@@ -209,6 +216,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_batch_config(self, group: int = 0, want_tiles: int = 0):
+        """Fields per shared batch launch (1..16) and wave tiles per field
+        (64..2^20); 0 restores a default."""
+        _check(_load().pcrit_set_batch_config(self._ptr, int(group), int(want_tiles)),
+               "set_batch_config")
+
+    def batch_config(self):
+        """(group, want_tiles) used by this context's batch calls."""
+        g, w = ctypes.c_int(0), ctypes.c_int64(0)
+        _check(_load().pcrit_get_batch_config(self._ptr, ctypes.byref(g), ctypes.byref(w)),
+               "get_batch_config")
+        return g.value, w.value
 
     def set_kernel_timing(self, levels=None):
         """Time the kernels of the given levels (iterable of ints), all
@@ -406,6 +426,48 @@ def classify_batch(fields, *, ctx: Optional[Context] = None, capacity: Optional[
     if check and st not in (0, E_CAPACITY):
         raise PcritError(st, "pcrit_classify_batch")
     return BatchResult(out_codes, crit, cc, offs, st)
+
+
+BATCH_TUNE_GROUPS = (8, 16)
+BATCH_TUNE_WANTS = (128, 256, 512, 1024, 2048, 4096)
+
+
+def batch_autotune(fields, *, ctx: Optional[Context] = None, reps: int = 3,
+                   capacity: Optional[int] = None, with_crit_codes: bool = False, stream=None):
+    """pcrit_batch_autotune: time the batch call on these fields for every
+    (group, want_tiles) in BATCH_TUNE_GROUPS x BATCH_TUNE_WANTS and keep the
+    fastest in the context.  Returns ((group, want_tiles), {(group,
+    want_tiles): ms per call}, codes, crit, crit_codes) -- the buffers hold
+    the batch's result."""
+    import torch
+    if len(fields) < 1:
+        raise PcritError(E_ARG, "empty batch")
+    dev = fields[0].device
+    c = _ctx_for(fields[0], ctx)
+    descs = (_BatchField * len(fields))()
+    total = 0
+    out_codes = []
+    for i, f in enumerate(fields):
+        if f.device != dev:
+            raise PcritError(E_ARG, "fields on different devices")
+        nx, ny, nz = _check_field(f)
+        cd = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
+        descs[i] = _BatchField(f.data_ptr(), nx, ny, nz, cd.data_ptr())
+        out_codes.append(cd)
+        total += f.numel()
+    capacity = _capacity(capacity, None, total)
+    crit = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    cc = (torch.empty(max(capacity, 1), dtype=torch.uint8, device=dev)
+          if with_crit_codes else None)
+    times = np.zeros(len(BATCH_TUNE_GROUPS) * len(BATCH_TUNE_WANTS), np.float64)
+    g, w = ctypes.c_int(0), ctypes.c_int64(0)
+    _check(_load().pcrit_batch_autotune(
+        c.handle, _stream_handle(fields[0], stream), len(fields), ctypes.addressof(descs),
+        _ptr(crit), _ptr(cc), int(capacity), int(reps), times.ctypes.data, ctypes.byref(g),
+        ctypes.byref(w)), "pcrit_batch_autotune")
+    table = {(gi, wi): float(times[k]) for k, (gi, wi) in
+             enumerate((gi, wi) for gi in BATCH_TUNE_GROUPS for wi in BATCH_TUNE_WANTS)}
+    return (g.value, w.value), table, out_codes, crit, cc
 
 
 def order_field(field, *, ctx: Optional[Context] = None, rank=None, sorted_out=None,

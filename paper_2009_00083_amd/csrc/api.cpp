@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/pcrit.h"
+#include "batch_tune.h"
 #include "pcrit_internal.h"
 #include "lts.h"
 
@@ -127,6 +128,9 @@ struct pcrit_ctx {
   int64_t ord_bytes = 0;
   void *lts = nullptr;  // merged-propagation records and saddle table
   int64_t lts_bytes = 0;
+  // batch launches: fields per shared launch, wave tiles per field
+  int batch_group = kBatchGroupDefault;
+  int64_t batch_want = kBatchWantDefault;
   // second stream (default priority) on which the learned order is scored
   // while the leading levels run, and the events that fork and join it
   hipStream_t side = nullptr;
@@ -206,6 +210,7 @@ struct Step {
   const float *f = nullptr;
   uint8_t *codes = nullptr;
   bool batch = false;
+  int64_t want = 0;  // batches: wave tiles per field (0: the launch's default)
   const Geom *prev = nullptr;  // previous (coarser) level, progressive only
   bool dirty = false;          // test old vertices against `prev`
   int mask_read = -1;          // masks slot holding prev's masks, or -1
@@ -292,7 +297,11 @@ int enqueue_group(pcrit_ctx *c, hipStream_t st, const float *field,
     // measured on 200 fields of 33..257 samples per axis, the fused
     // kernel's 8-plane tiles take 2.15 ms, the plain kernel's 24-plane tiles
     // 2.31 ms
-    if (dim == 3)
+    if (sp.want > 0 && dim == 3)
+      plan_level3_want(d, fused || steps[0].mask_write >= 0, sp.want);
+    else if (sp.want > 0)
+      plan_level2_want(d, sp.want);
+    else if (dim == 3)
       plan_level3(d, fused || steps[0].mask_write >= 0, fused);
     else
       plan_level2(d, fused);
@@ -1220,11 +1229,13 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
     sp.f = fd.field;
     sp.codes = fd.codes;
     sp.batch = true;
+    sp.want = c->batch_want;
     sp.slot = i;
   }
+  const int G = c->batch_group;
   // scratch for the largest group
-  for (int i0 = 0; i0 < n_fields; i0 += kMaxFused) {
-    const int n = std::min(kMaxFused, n_fields - i0);
+  for (int i0 = 0; i0 < n_fields; i0 += G) {
+    const int n = std::min(G, n_fields - i0);
     int64_t w, ch, lb;
     launch_needs(&steps[(size_t)i0], n, false, &w, &ch, &lb);
     words = std::max(words, w);
@@ -1235,7 +1246,7 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
   // More than one group: group g+1 is classified on hip_stream while group
   // g is compacted on the side stream (compactions in order there, so the
   // lists still land in field order), each group on scratch set g % 2.
-  const int ngroups = (n_fields + kMaxFused - 1) / kMaxFused;
+  const int ngroups = (n_fields + G - 1) / G;
   const bool piped = ngroups > 1;
   int st = ensure((void **)&c->bits, &c->bits_words, words * 8);
   if (!st) st = ensure((void **)&c->counts, &c->counts_n, chunks * (int64_t)sizeof(int));
@@ -1253,8 +1264,8 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
   if (launch_zero_i64(off, 1, s) != hipSuccess) return PCRIT_E_HIP;
   const unsigned gen = next_gen(c);
   reset_kernel_marks(c);
-  for (int i0 = 0, g = 0; i0 < n_fields; i0 += kMaxFused, g++) {
-    const int n = std::min(kMaxFused, n_fields - i0);
+  for (int i0 = 0, g = 0; i0 < n_fields; i0 += G, g++) {
+    const int n = std::min(G, n_fields - i0);
     const int k = g & 1;
     // set k is free once group g-2's compaction is done
     if (piped && g >= 2 && hipStreamWaitEvent(s, c->ev_cmp[k], 0) != hipSuccess)
@@ -1276,6 +1287,94 @@ int pcrit_classify_batch(pcrit_ctx *c, void *hip_stream, int n_fields,
     return PCRIT_E_HIP;
   if (c->h_flags[0] == gen) return PCRIT_E_NAN;
   return offsets_host[n_fields] > crit_capacity ? PCRIT_E_CAPACITY : PCRIT_OK;
+}
+
+// ------------------------------------------------------------------------
+// Batch launch configuration and its autotuner.
+int pcrit_set_batch_config(pcrit_ctx *c, int group, int64_t want_tiles) {
+  if (!c || group < 0 || group > PCRIT_BATCH_GROUP_MAX || want_tiles < 0 ||
+      (want_tiles > 0 && (want_tiles < kBatchWantMin || want_tiles > kBatchWantMax)))
+    return PCRIT_E_ARG;
+  c->batch_group = group ? group : kBatchGroupDefault;
+  c->batch_want = want_tiles ? want_tiles : kBatchWantDefault;
+  return PCRIT_OK;
+}
+
+int pcrit_get_batch_config(pcrit_ctx *c, int *group, int64_t *want_tiles) {
+  if (!c || !group || !want_tiles) return PCRIT_E_ARG;
+  *group = c->batch_group;
+  *want_tiles = c->batch_want;
+  return PCRIT_OK;
+}
+
+int pcrit_batch_autotune(pcrit_ctx *c, void *hip_stream, int n_fields,
+                         const pcrit_batch_field *fields_host, uint32_t *crit,
+                         uint8_t *crit_codes, int64_t crit_capacity, int reps,
+                         double *times_ms_host, int *group_out, int64_t *want_out) {
+  static const int kGroups[] = {8, 16};
+  static const int64_t kWants[] = {128, 256, 512, 1024, 2048, 4096};
+  static_assert(sizeof(kGroups) / sizeof(kGroups[0]) * sizeof(kWants) / sizeof(kWants[0]) ==
+                    PCRIT_BATCH_TUNE_CANDIDATES,
+                "candidate count");
+  if (!c || reps < 1 || reps > 100) return PCRIT_E_ARG;
+  const int g0 = c->batch_group;
+  const int64_t w0 = c->batch_want;
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<int64_t> off((size_t)std::max(n_fields, 0) + 1);
+  // one checked call first: arguments, capacity and NaN, with the current
+  // configuration
+  int st = pcrit_classify_batch(c, hip_stream, n_fields, fields_host, crit, crit_codes,
+                                crit_capacity, off.data(), nullptr);
+  if (st) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return PCRIT_E_HIP;
+  }
+  double best = -1.0;
+  int bg = g0;
+  int64_t bw = w0;
+  int k = 0;
+  for (int gi : kGroups)
+    for (int64_t wi : kWants) {
+      c->batch_group = gi;
+      c->batch_want = wi;
+      // an untimed call grows the scratch this configuration needs
+      st = pcrit_classify_batch(c, hip_stream, n_fields, fields_host, crit, crit_codes,
+                                crit_capacity, nullptr, nullptr);
+      if (!st && hipEventRecord(e0, s) != hipSuccess) st = PCRIT_E_HIP;
+      for (int r = 0; r < reps && !st; r++)
+        st = pcrit_classify_batch(c, hip_stream, n_fields, fields_host, crit, crit_codes,
+                                  crit_capacity, nullptr, nullptr);
+      float ms = 0.f;
+      if (!st && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = PCRIT_E_HIP;
+      if (st) break;
+      const double per = (double)ms / reps;
+      if (times_ms_host) times_ms_host[k] = per;
+      if (best < 0 || per < best) {
+        best = per;
+        bg = gi;
+        bw = wi;
+      }
+      k++;
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) {
+    c->batch_group = g0;
+    c->batch_want = w0;
+    return st;
+  }
+  c->batch_group = bg;
+  c->batch_want = bw;
+  if (group_out) *group_out = bg;
+  if (want_out) *want_out = bw;
+  // leave the caller's buffers holding the batch's result (the same under
+  // every configuration)
+  return pcrit_classify_batch(c, hip_stream, n_fields, fields_host, crit, crit_codes,
+                              crit_capacity, off.data(), nullptr);
 }
 
 // ------------------------------------------------------------------------

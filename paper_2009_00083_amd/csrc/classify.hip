@@ -11,6 +11,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "batch_tune.h"
 #include "device_util.h"
 #include "pcrit_internal.h"
 
@@ -1126,24 +1127,30 @@ int tile_depth(int64_t columns, int n, int cap, int step, int64_t want) {
 
 }  // namespace
 
-void plan_level3(LevelDesc &l, bool write_masks, bool fused) {
+void plan_level3_want(LevelDesc &l, bool write_masks, int64_t want) {
   l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = (l.my + kTile3Y - 1) / kTile3Y;
-  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, zchunk_cap3(write_masks), kUnroll3,
-                        fused ? kWantTilesFused : kWantTilesLevel);
+  l.zchunk = tile_depth((int64_t)l.ntx * l.nty, l.mz, zchunk_cap3(write_masks), kUnroll3, want);
   l.ntiles = l.ntx * l.nty * ((l.mz + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor((uint32_t)l.nty, &l.nty_mul, &l.nty_shift);
 }
 
-void plan_level2(LevelDesc &l, bool fused) {
+void plan_level2_want(LevelDesc &l, int64_t want) {
   l.ntx = (l.mx + kTileCols - 1) / kTileCols;
   l.nty = 1;
-  l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2,
-                        fused ? kWantTilesFused : kWantTilesLevel);
+  l.zchunk = tile_depth(l.ntx, l.my, kYChunk2, kUnroll2, want);
   l.ntiles = l.ntx * ((l.my + l.zchunk - 1) / l.zchunk);
   fast_divisor((uint32_t)l.ntx, &l.ntx_mul, &l.ntx_shift);
   fast_divisor(1u, &l.nty_mul, &l.nty_shift);
+}
+
+void plan_level3(LevelDesc &l, bool write_masks, bool fused) {
+  plan_level3_want(l, write_masks, fused ? kWantTilesFused : kWantTilesLevel);
+}
+
+void plan_level2(LevelDesc &l, bool fused) {
+  plan_level2_want(l, fused ? kWantTilesFused : kWantTilesLevel);
 }
 
 hipError_t launch_classify(const ClassifyArgs &a, int dim, bool read_prev,

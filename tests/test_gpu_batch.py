@@ -137,3 +137,76 @@ def test_batch_in_captured_graph(ctx, dev):
         assert torch.equal(crit[:n], ref.crit[:n]), rep
         for c, r in zip(codes, ref.codes):
             assert torch.equal(c, r), rep
+
+
+# ---------------------------------------------------------------------------
+# launch configuration and its autotuner
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_batch_configurations_give_the_same_result(dev, dim):
+    """Fields per launch (1 .. 16, a ragged last group) and wave tiles per
+    field (64 .. 2^20: deepest tiles down to single-step tiles) change the
+    launches, never the result: lists, codes, list codes and offsets equal
+    the default configuration's, which equals the oracle's."""
+    ctx = pc.Context(0)
+    fs = _fields(300 + dim, 23, dim, 3, 60 if dim == 3 else 400)
+    ts = [torch.from_numpy(f).to(dev) for f in fs]
+    assert ctx.batch_config() == (16, 512)
+    ref = pc.classify_batch(ts, ctx=ctx, with_crit_codes=True)
+    torch.cuda.synchronize()
+    for i, f in enumerate(fs):
+        assert np.array_equal(ref.field_list(i).cpu().numpy().view(np.uint32), oracle.classify(f).crit)
+    n = int(ref.offsets[-1])
+    for group, want in ((1, 64), (3, 512), (5, 0), (16, 1 << 20), (7, 100), (0, 8192)):
+        ctx.set_batch_config(group, want)
+        log("batch config", dim, ctx.batch_config())
+        r = pc.classify_batch(ts, ctx=ctx, with_crit_codes=True)
+        torch.cuda.synchronize()
+        assert r.status == 0 and np.array_equal(r.offsets, ref.offsets), (group, want)
+        assert torch.equal(r.crit[:n], ref.crit[:n]) and torch.equal(r.crit_codes[:n], ref.crit_codes[:n])
+        for a, b in zip(r.codes, ref.codes):
+            assert torch.equal(a, b), (group, want)
+    ctx.set_batch_config(0, 0)
+    assert ctx.batch_config() == (16, 512)
+
+
+def test_batch_config_arguments(dev):
+    ctx = pc.Context(0)
+    for group, want in ((17, 0), (-1, 0), (0, 63), (0, (1 << 20) + 1), (0, -5)):
+        with pytest.raises(pc.PcritError) as e:
+            ctx.set_batch_config(group, want)
+        assert e.value.status == pc.E_ARG
+    assert ctx.batch_config() == (16, 512)
+
+
+def test_batch_autotune(dev):
+    """The tuner times every candidate, keeps the fastest in the context, and
+    leaves the batch's result in its buffers; later batch calls use the
+    choice and give the same result; a batch error comes back unchanged and
+    leaves the configuration alone."""
+    ctx = pc.Context(0)
+    fs = _fields(401, 40, 3, 20, 80)
+    ts = [torch.from_numpy(f).to(dev) for f in fs]
+    ref = pc.classify_batch(ts, ctx=ctx)
+    torch.cuda.synchronize()
+    n = int(ref.offsets[-1])
+    choice, table, codes, crit, _ = pc.batch_autotune(ts, ctx=ctx, reps=2)
+    torch.cuda.synchronize()
+    log("autotune", choice, {k: round(v, 3) for k, v in table.items()})
+    assert len(table) == pc.binding.BATCH_TUNE_GROUPS.__len__() * len(pc.binding.BATCH_TUNE_WANTS)
+    assert all(v > 0 for v in table.values())
+    assert choice in table and table[choice] == min(table.values())
+    assert ctx.batch_config() == choice
+    assert torch.equal(crit[:n], ref.crit[:n])
+    for a, b in zip(codes, ref.codes):
+        assert torch.equal(a, b)
+    r = pc.classify_batch(ts, ctx=ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(r.offsets, ref.offsets) and torch.equal(r.crit[:n], ref.crit[:n])
+    # capacity too small: the checking call fails, the configuration stays
+    ctx.set_batch_config(4, 512)
+    with pytest.raises(pc.PcritError) as e:
+        pc.batch_autotune(ts, ctx=ctx, reps=1, capacity=n - 1)
+    assert e.value.status == pc.E_CAPACITY
+    assert ctx.batch_config() == (4, 512)
