@@ -56,6 +56,22 @@ __device__ __forceinline__ int64_t neighbour(const Grid &g, uint32_t x, uint32_t
   return (int64_t)((c * g.ny + b) * g.nx + a);
 }
 
+// A 128-bit Bloom filter of the vertices a propagation has taken or let
+// wait (a vertex never leaves that set): a clear bit proves a vertex new,
+// so the scans of the component and the waiting set run only on a set bit.
+__device__ __forceinline__ uint32_t seen_bit(uint32_t u) { return (u * 0x9E3779B1u) >> 25; }
+__device__ __forceinline__ void seen_mark(uint64_t &s0, uint64_t &s1, uint32_t u) {
+  const uint32_t b = seen_bit(u);
+  if (b < 64)
+    s0 |= 1ull << b;
+  else
+    s1 |= 1ull << (b - 64);
+}
+__device__ __forceinline__ bool seen_maybe(uint64_t s0, uint64_t s1, uint32_t u) {
+  const uint32_t b = seen_bit(u);
+  return ((b < 64 ? s0 : s1) >> (b & 63)) & 1;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void lts_propagate_kernel(
     const float *f, const uint32_t *rank, Grid g, const uint32_t *ext, int64_t n_ext,
@@ -76,6 +92,8 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
   uint32_t wv[kLtsMaxFrontier + 14], wk[kLtsMaxFrontier + 14];
   int nc = 1, nw = 0;
   comp[0] = (uint32_t)m;
+  uint64_t s0 = 0, s1 = 0;
+  seen_mark(s0, s1, (uint32_t)m);
   const float fm = f[m];
   auto key = [&](int64_t u) { return rank[u] ^ flip; };
   auto in_comp = [&](uint32_t u) {
@@ -96,6 +114,7 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
       if (u < 0) continue;
       wv[nw] = (uint32_t)u;
       wk[nw] = key(u);
+      seen_mark(s0, s1, (uint32_t)u);
       nw++;
     }
   }
@@ -132,7 +151,9 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
     bool is_saddle = false;
 #pragma unroll
     for (int k = 0; k < NB; k++)
-      if (!is_saddle && nu[k] >= 0 && nk[k] > kv && !in_comp((uint32_t)nu[k])) is_saddle = true;
+      if (!is_saddle && nu[k] >= 0 && nk[k] > kv &&
+          !(seen_maybe(s0, s1, (uint32_t)nu[k]) && in_comp((uint32_t)nu[k])))
+        is_saddle = true;
     if (is_saddle) {
       st = kLtsSaddle;
       sd = (int32_t)v;
@@ -141,9 +162,12 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
     if (nc >= max_visited) break;
 #pragma unroll
     for (int k = 0; k < NB; k++) {
-      if (nu[k] < 0 || nk[k] > kv || waiting((uint32_t)nu[k])) continue;
+      if (nu[k] < 0 || nk[k] > kv ||
+          (seen_maybe(s0, s1, (uint32_t)nu[k]) && waiting((uint32_t)nu[k])))
+        continue;
       wv[nw] = (uint32_t)nu[k];
       wk[nw] = nk[k];
+      seen_mark(s0, s1, (uint32_t)nu[k]);
       nw++;
     }
     if (nw > max_frontier) break;
@@ -225,6 +249,9 @@ struct Prop {
   int nc, nw;
   uint32_t lead;
   float fl;
+  uint64_t s0, s1;  // Bloom filter of comp and the waiting vertices
+  __device__ void mark(uint32_t u) { seen_mark(s0, s1, u); }
+  __device__ bool maybe(uint32_t u) const { return seen_maybe(s0, s1, u); }
   __device__ bool in_comp(uint32_t u) const {
     for (int j = 0; j < nc; j++)
       if (comp[j] == u) return true;
@@ -286,7 +313,7 @@ __device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
     for (int k = 0; k < NB; k++) {
       if (nu[k] >= 0 && nk[k] > kv) {
         nh++;
-        mine += p.in_comp((uint32_t)nu[k]) ? 1u : 0u;
+        mine += p.maybe((uint32_t)nu[k]) && p.in_comp((uint32_t)nu[k]) ? 1u : 0u;
       }
     }
     if (mine < nh) {  // arrival at the saddle v
@@ -318,9 +345,11 @@ __device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
     }
 #pragma unroll
     for (int k = 0; k < NB; k++) {
-      if (nu[k] < 0 || nk[k] > kv || p.waiting((uint32_t)nu[k])) continue;
+      if (nu[k] < 0 || nk[k] > kv || (p.maybe((uint32_t)nu[k]) && p.waiting((uint32_t)nu[k])))
+        continue;
       p.wv[p.nw] = (uint32_t)nu[k];
       p.wk[p.nw] = nk[k];
+      p.mark((uint32_t)nu[k]);
       p.nw++;
     }
     if (p.nw > a.max_frontier) {
@@ -342,6 +371,8 @@ __global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
   Prop p;
   p.nc = 1;
   p.nw = 0;
+  p.s0 = p.s1 = 0;
+  p.mark((uint32_t)m);
   if (ok) {  // the neighbours wait; an extremum of the kind asked for comes after all of them
     uint32_t x, y, z;
     coords(a.g, (uint32_t)m, x, y, z);
@@ -351,6 +382,7 @@ __global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
       if (u < 0) continue;
       p.wv[p.nw] = (uint32_t)u;
       p.wk[p.nw] = key(u);
+      p.mark((uint32_t)u);
       ok = ok && p.wk[p.nw] < km;
       p.nw++;
     }
@@ -402,13 +434,18 @@ __global__ __launch_bounds__(256) void lts_merge_round_kernel(MergeArgs a, int r
     }
     p.nc = 0;
     p.nw = 0;
+    p.s0 = p.s1 = 0;
     p.comp[p.nc++] = v;
+    p.mark(v);
     for (uint32_t q = head, step = 0; q < (uint32_t)a.n_ext && step < kMaxArrivals;
          q = a.rec[(size_t)q * kRecWords + 3], step++) {
       const uint32_t *o = a.rec + (size_t)q * kRecWords;
       const int on = (int)min(o[0], (uint32_t)kLtsMaxVisited);
       for (int j = 0; j < on && p.nc < kLtsMaxVisited; j++)
-        if (o[4 + j] != v) p.comp[p.nc++] = o[4 + j];
+        if (o[4 + j] != v) {
+          p.mark(o[4 + j]);
+          p.comp[p.nc++] = o[4 + j];
+        }
     }
     bool over = false;
     for (uint32_t q = head, step = 0; q < (uint32_t)a.n_ext && step < kMaxArrivals && !over;
@@ -417,9 +454,10 @@ __global__ __launch_bounds__(256) void lts_merge_round_kernel(MergeArgs a, int r
       const int ow = (int)min(o[1], (uint32_t)kLtsMaxFrontier);
       for (int j = 0; j < ow && !over; j++) {
         const uint32_t u = o[4 + kLtsMaxVisited + j];
-        if (u >= a.g.n || p.in_comp(u) || p.waiting(u)) continue;
+        if (u >= a.g.n || (p.maybe(u) && (p.in_comp(u) || p.waiting(u)))) continue;
         p.wv[p.nw] = u;
         p.wk[p.nw] = key(u);
+        p.mark(u);
         over = ++p.nw > a.max_frontier;
       }
     }
@@ -427,9 +465,11 @@ __global__ __launch_bounds__(256) void lts_merge_round_kernel(MergeArgs a, int r
     coords(a.g, (uint32_t)v, x, y, z);
     for (int k = 0; k < NB && !over; k++) {  // the saddle's own neighbours
       const int64_t u = neighbour<DIM>(a.g, x, y, z, k);
-      if (u < 0 || p.in_comp((uint32_t)u) || p.waiting((uint32_t)u)) continue;
+      if (u < 0 || (p.maybe((uint32_t)u) && (p.in_comp((uint32_t)u) || p.waiting((uint32_t)u))))
+        continue;
       p.wv[p.nw] = (uint32_t)u;
       p.wk[p.nw] = key(u);
+      p.mark((uint32_t)u);
       over = ++p.nw > a.max_frontier;
     }
     if (over) {
