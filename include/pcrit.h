@@ -507,7 +507,8 @@ int pcrit_extrema(pcrit_ctx *ctx, void *hip_stream, const uint8_t *codes, int64_
  * n_extrema entries each): status (uint8), saddle (int32 index, -1 unless
  * a saddle stop) and visited (uint16, vertices taken, the extremum
  * included).  Every extremum propagates on its own (propagations that meet
- * at a saddle are not merged).  Asynchronous: kernels only, no wait.
+ * at a saddle are not merged; pcrit_lts_merged merges them).
+ * Asynchronous: kernels only, no wait.
  * PCRIT_E_ARG for NULL or misaligned pointers, a NaN epsilon or budgets
  * out of range; dims as for pcrit_classify. */
 int pcrit_lts_propagate(pcrit_ctx *ctx, void *hip_stream, const float *field,
