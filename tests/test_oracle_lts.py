@@ -268,3 +268,26 @@ def test_merged_invalid_entries():
     st, sd, vi = lts.propagate_merged(f, [int(mx[0]), f.size, notmax, int(mx[1])], 0.1)
     assert list(st[1:3]) == [lts.INVALID, lts.INVALID] and list(sd[1:3]) == [-1, -1]
     assert list(vi[1:3]) == [0, 0]
+
+
+def test_merged_budget_at_a_merge():
+    """The budget reading at a merge, on the two-peak profile: the higher
+    peak reaches the pass with 36 vertices, the lower one with 22, so their
+    union holds 57.  With max_visited 57 the union itself is over budget
+    (the merge ends it, visited 57); with 58 the merged propagation takes
+    one more vertex before the budget stops it; with 35 the higher peak
+    never reaches the pass."""
+    ny, cy = 7, 3
+    y = np.arange(ny)[:, None]
+    g = np.array([0, 0.5, 1, 0.7, 0.6, 0.5, 1.2, 1.6, 2, 1.5, 1], np.float32)
+    f = (g[None, :] - 0.01 * np.abs(y - cy)).astype(np.float32)
+    pk = [cy * 11 + 2, cy * 11 + 8]
+    rank, _ = order_field(f)
+    pass_v = cy * 11 + 5
+    comp_hi = lts.superlevel_component(f.shape, rank.astype(np.int64), pk[1], int(rank[pass_v]) + 1)
+    comp_lo = lts.superlevel_component(f.shape, rank.astype(np.int64), pk[0], int(rank[pass_v]) + 1)
+    assert (len(comp_hi) + 1, len(comp_lo) + 1) == (36, 22)
+    for mv, visited_hi in ((57, 57), (58, 58), (36, 57), (35, 35)):
+        st, sd, vi = lts.propagate_merged(f, pk, np.inf, True, mv, 1000)
+        assert list(st) == [lts.SADDLE, lts.BUDGET] and sd[0] == pass_v, mv
+        assert list(vi) == [22, visited_hi], mv
