@@ -11,9 +11,12 @@
 // or when the component holds max_visited vertices or more than
 // max_frontier vertices wait outside it (budget).  Component and waiting
 // vertices live in per-thread arrays (private memory); membership is a
-// linear scan, which stays cheap for the small components that noise
-// extrema have.  The propagations are independent: merging propagations
-// that meet at a saddle (hill chains) is not done here.
+// linear scan behind a 128-bit Bloom filter, which stays cheap for the
+// small components that noise extrema have.
+//
+// lts_propagate_kernel runs every propagation on its own.  The merged
+// kernels further down (Section 4.4) let the propagations that meet at a
+// saddle go on as one, in rounds.
 #include <stdint.h>
 
 #include <algorithm>
