@@ -75,6 +75,21 @@ __device__ __forceinline__ bool seen_maybe(uint64_t s0, uint64_t s1, uint32_t u)
   return ((b < 64 ? s0 : s1) >> (b & 63)) & 1;
 }
 
+// Membership in a[0 .. n): four entries per step, no early exit (the loads
+// of a step issue together).  The arrays hold a multiple of four entries,
+// so the reads past n stay inside them; their entries are masked out.
+constexpr int kWaitCap = kLtsMaxFrontier + 16;  // waiting vertices: up to max_frontier + 14
+static_assert(kWaitCap % 4 == 0 && kLtsMaxVisited % 4 == 0, "scans read four entries at a time");
+__device__ __forceinline__ bool scan4(const uint32_t *a, int n, uint32_t u) {
+  bool f = false;
+  for (int j = 0; j < n; j += 4) {
+    const uint32_t a0 = a[j], a1 = a[j + 1], a2 = a[j + 2], a3 = a[j + 3];
+    f |= (a0 == u) | ((j + 1 < n) & (a1 == u)) | ((j + 2 < n) & (a2 == u)) |
+         ((j + 3 < n) & (a3 == u));
+  }
+  return f;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void lts_propagate_kernel(
     const float *f, const uint32_t *rank, Grid g, const uint32_t *ext, int64_t n_ext,
@@ -92,23 +107,15 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
   }
   const bool maxima = flip == 0u;
   uint32_t comp[kLtsMaxVisited];
-  uint32_t wv[kLtsMaxFrontier + 14], wk[kLtsMaxFrontier + 14];
+  uint32_t wv[kWaitCap], wk[kWaitCap];
   int nc = 1, nw = 0;
   comp[0] = (uint32_t)m;
   uint64_t s0 = 0, s1 = 0;
   seen_mark(s0, s1, (uint32_t)m);
   const float fm = f[m];
   auto key = [&](int64_t u) { return rank[u] ^ flip; };
-  auto in_comp = [&](uint32_t u) {
-    for (int j = 0; j < nc; j++)
-      if (comp[j] == u) return true;
-    return false;
-  };
-  auto waiting = [&](uint32_t u) {
-    for (int j = 0; j < nw; j++)
-      if (wv[j] == u) return true;
-    return false;
-  };
+  auto in_comp = [&](uint32_t u) { return scan4(comp, nc, u); };
+  auto waiting = [&](uint32_t u) { return scan4(wv, nw, u); };
   {
     uint32_t x, y, z;
     coords(g, (uint32_t)m, x, y, z);
@@ -248,23 +255,15 @@ __global__ __launch_bounds__(256) void lts_table_clear_kernel(uint32_t *tkey, ui
 // The per-thread state of one propagation.
 struct Prop {
   uint32_t comp[kLtsMaxVisited];
-  uint32_t wv[kLtsMaxFrontier + 14], wk[kLtsMaxFrontier + 14];
+  uint32_t wv[kWaitCap], wk[kWaitCap];
   int nc, nw;
   uint32_t lead;
   float fl;
   uint64_t s0, s1;  // Bloom filter of comp and the waiting vertices
   __device__ void mark(uint32_t u) { seen_mark(s0, s1, u); }
   __device__ bool maybe(uint32_t u) const { return seen_maybe(s0, s1, u); }
-  __device__ bool in_comp(uint32_t u) const {
-    for (int j = 0; j < nc; j++)
-      if (comp[j] == u) return true;
-    return false;
-  }
-  __device__ bool waiting(uint32_t u) const {
-    for (int j = 0; j < nw; j++)
-      if (wv[j] == u) return true;
-    return false;
-  }
+  __device__ bool in_comp(uint32_t u) const { return scan4(comp, nc, u); }
+  __device__ bool waiting(uint32_t u) const { return scan4(wv, nw, u); }
 };
 
 __device__ __forceinline__ void finish(const MergeArgs &a, uint32_t lead, uint8_t st, int nc) {
