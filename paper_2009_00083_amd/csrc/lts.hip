@@ -90,6 +90,33 @@ __device__ __forceinline__ bool scan4(const uint32_t *a, int n, uint32_t u) {
   return f;
 }
 
+// Index of the largest of k[0 .. n) (n >= 1; the keys are distinct ranks),
+// four keys per step, the running maximum in a register.
+__device__ __forceinline__ int argmax4(const uint32_t *k, int n) {
+  int b = 0;
+  uint32_t kb = k[0];
+  for (int j = 0; j < n; j += 4) {
+    const uint32_t k0 = k[j], k1 = k[j + 1], k2 = k[j + 2], k3 = k[j + 3];
+    if (k0 > kb) {
+      kb = k0;
+      b = j;
+    }
+    if (j + 1 < n && k1 > kb) {
+      kb = k1;
+      b = j + 1;
+    }
+    if (j + 2 < n && k2 > kb) {
+      kb = k2;
+      b = j + 2;
+    }
+    if (j + 3 < n && k3 > kb) {
+      kb = k3;
+      b = j + 3;
+    }
+  }
+  return b;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void lts_propagate_kernel(
     const float *f, const uint32_t *rank, Grid g, const uint32_t *ext, int64_t n_ext,
@@ -132,9 +159,7 @@ __global__ __launch_bounds__(256) void lts_propagate_kernel(
   int32_t sd = -1;
   while (nw > 0) {
     // take the largest waiting vertex
-    int b = 0;
-    for (int j = 1; j < nw; j++)
-      if (wk[j] > wk[b]) b = j;
+    const int b = argmax4(wk, nw);
     const uint32_t v = wv[b], kv = wk[b];
     wv[b] = wv[nw - 1];
     wk[b] = wk[nw - 1];
@@ -285,9 +310,7 @@ __device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
       finish(a, p.lead, kLtsPersistent, p.nc);
       return;
     }
-    int b = 0;
-    for (int j = 1; j < p.nw; j++)
-      if (p.wk[j] > p.wk[b]) b = j;
+    const int b = argmax4(p.wk, p.nw);
     const uint32_t v = p.wv[b], kv = p.wk[b];
     p.wv[b] = p.wv[p.nw - 1];
     p.wk[b] = p.wk[p.nw - 1];
