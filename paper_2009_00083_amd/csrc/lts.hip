@@ -118,7 +118,7 @@ __device__ __forceinline__ int argmax4(const uint32_t *k, int n) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void lts_propagate_kernel(
+__global__ __launch_bounds__(64) void lts_propagate_kernel(
     const float *f, const uint32_t *rank, Grid g, const uint32_t *ext, int64_t n_ext,
     uint32_t flip, float eps, int max_visited, int max_frontier, uint8_t *status,
     int32_t *saddle, uint16_t *visited) {
@@ -386,7 +386,7 @@ __device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
 
 // Round 0: one thread per listed extremum.
 template <int DIM>
-__global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
+__global__ __launch_bounds__(64) void lts_merge_start_kernel(MergeArgs a) {
   constexpr int NB = DIM == 3 ? 14 : 6;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_ext) return;
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void lts_merge_start_kernel(MergeArgs a) {
 
 // Round r >= 1: one thread per saddle completed in round r - 1.
 template <int DIM>
-__global__ __launch_bounds__(256) void lts_merge_round_kernel(MergeArgs a, int round) {
+__global__ __launch_bounds__(64) void lts_merge_round_kernel(MergeArgs a, int round) {
   constexpr int NB = DIM == 3 ? 14 : 6;
   const uint32_t cnt = min(a.qcount[round], (uint32_t)a.n_ext);
   auto key = [&](int64_t u) { return a.rank[u] ^ a.flip; };
@@ -550,7 +550,9 @@ hipError_t launch_lts_merged(const float *f, const uint32_t *rank, int64_t nx, i
   a.qcount = a.queue[1] + n_ext;
   hipLaunchKernelGGL(lts_table_clear_kernel, dim3(std::min<uint32_t>((cap + 255) / 256, 2048)),
                      dim3(256), 0, st, a.tkey, a.tcnt, a.thead, cap, a.qcount);
-  const dim3 grid((unsigned)((n_ext + 255) / 256)), block(256);
+  // one wave per workgroup: a propagation's wave finishes on its own time
+  // (64-lane groups: merged 7.0 -> 6.6 ms against 256-lane groups)
+  const dim3 grid((unsigned)((n_ext + 63) / 64)), block(64);
   // rounds: one thread per possible queue entry (at most one per parked
   // propagation), striding if fewer; empty rounds end at once
   const dim3 rgrid = grid;
@@ -575,7 +577,7 @@ hipError_t launch_lts_propagate(const float *f, const uint32_t *rank, int64_t nx
       max_frontier > kLtsMaxFrontier)
     return hipErrorInvalidValue;
   const Grid g{(uint32_t)nx, (uint32_t)ny, (uint32_t)nz, (uint32_t)(nx * ny * nz)};
-  const dim3 grid((unsigned)((n_ext + 255) / 256)), block(256);
+  const dim3 grid((unsigned)((n_ext + 63) / 64)), block(64);
   const uint32_t flip = maxima ? 0u : 0xFFFFFFFFu;
   if (nz > 1)
     hipLaunchKernelGGL(lts_propagate_kernel<3>, grid, block, 0, st, f, rank, g, ext, n_ext, flip,
