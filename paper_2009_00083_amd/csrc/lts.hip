@@ -233,6 +233,7 @@ __global__ __launch_bounds__(64) void lts_propagate_kernel(
 // vertices stops at the budget, so max_visited rounds after round 0 finish
 // every propagation.
 constexpr int kRecWords = 4 + kLtsMaxVisited + kLtsMaxFrontier;
+static_assert(kRecWords % 4 == 0 && kLtsMaxVisited % 4 == 0, "records of 16-byte blocks");
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 // arrivals at one saddle: each holds one of its (at most 14) higher neighbours
 constexpr uint32_t kMaxArrivals = 16;
@@ -346,8 +347,16 @@ __device__ void advance(const MergeArgs &a, int round, uint32_t own, Prop &p) {
       r[0] = (uint32_t)p.nc;
       r[1] = (uint32_t)p.nw;
       r[2] = p.lead;
-      for (int j = 0; j < p.nc; j++) r[4 + j] = p.comp[j];
-      for (int j = 0; j < p.nw; j++) r[4 + kLtsMaxVisited + j] = p.wv[j];
+      // whole 16-byte blocks: the record is 16-byte aligned (656 bytes), its
+      // areas start on block boundaries and hold the last partial block
+      // (at most 32 taken, fewer than 128 waiting at an arrival); words past
+      // the counts are never read
+      for (int j = 0; j < p.nc; j += 4)
+        *reinterpret_cast<uint4 *>(r + 4 + j) =
+            make_uint4(p.comp[j], p.comp[j + 1], p.comp[j + 2], p.comp[j + 3]);
+      for (int j = 0; j < p.nw; j += 4)
+        *reinterpret_cast<uint4 *>(r + 4 + kLtsMaxVisited + j) =
+            make_uint4(p.wv[j], p.wv[j + 1], p.wv[j + 2], p.wv[j + 3]);
       a.status[p.lead] = kLtsSaddle;  // final unless a merge picks this leader
       a.saddle[p.lead] = (int32_t)v;
       a.visited[p.lead] = (uint16_t)p.nc;
