@@ -475,24 +475,36 @@ __global__ __launch_bounds__(64) void lts_merge_round_kernel(MergeArgs a, int ro
          q = a.rec[(size_t)q * kRecWords + 3], step++) {
       const uint32_t *o = a.rec + (size_t)q * kRecWords;
       const int on = (int)min(o[0], (uint32_t)kLtsMaxVisited);
-      for (int j = 0; j < on && p.nc < kLtsMaxVisited; j++)
-        if (o[4 + j] != v) {
-          p.mark(o[4 + j]);
-          p.comp[p.nc++] = o[4 + j];
-        }
+      for (int j = 0; j < on; j += 4) {  // 16-byte blocks, as written
+        const uint4 c4 = *reinterpret_cast<const uint4 *>(o + 4 + j);
+        const uint32_t cs[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+          if (j + t < on && cs[t] != v && p.nc < kLtsMaxVisited) {
+            p.mark(cs[t]);
+            p.comp[p.nc++] = cs[t];
+          }
+      }
     }
     bool over = false;
     for (uint32_t q = head, step = 0; q < (uint32_t)a.n_ext && step < kMaxArrivals && !over;
          q = a.rec[(size_t)q * kRecWords + 3], step++) {
       const uint32_t *o = a.rec + (size_t)q * kRecWords;
       const int ow = (int)min(o[1], (uint32_t)kLtsMaxFrontier);
-      for (int j = 0; j < ow && !over; j++) {
-        const uint32_t u = o[4 + kLtsMaxVisited + j];
-        if (u >= a.g.n || (p.maybe(u) && (p.in_comp(u) || p.waiting(u)))) continue;
-        p.wv[p.nw] = u;
-        p.wk[p.nw] = key(u);
-        p.mark(u);
-        over = ++p.nw > a.max_frontier;
+      for (int j = 0; j < ow && !over; j += 4) {
+        const uint4 f4 = *reinterpret_cast<const uint4 *>(o + 4 + kLtsMaxVisited + j);
+        const uint32_t fs[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const uint32_t u = fs[t];
+          if (over || j + t >= ow || u >= a.g.n ||
+              (p.maybe(u) && (p.in_comp(u) || p.waiting(u))))
+            continue;
+          p.wv[p.nw] = u;
+          p.wk[p.nw] = key(u);
+          p.mark(u);
+          over = ++p.nw > a.max_frontier;
+        }
       }
     }
     uint32_t x, y, z;
