@@ -574,9 +574,10 @@ hipError_t launch_lts_merged(const float *f, const uint32_t *rank, int64_t nx, i
   // one wave per workgroup: a propagation's wave finishes on its own time
   // (64-lane groups: merged 7.0 -> 6.6 ms against 256-lane groups)
   const dim3 grid((unsigned)((n_ext + 63) / 64)), block(64);
-  // rounds: one thread per possible queue entry (at most one per parked
-  // propagation), striding if fewer; empty rounds end at once
-  const dim3 rgrid = grid;
+  // rounds: at most 8192 one-wave groups striding over the queue (an empty
+  // round is one short launch; a full grid of n_ext threads cost 12 us per
+  // empty round)
+  const dim3 rgrid((unsigned)std::min<int64_t>(((int64_t)n_ext + 63) / 64, 8192));
   if (nz > 1) {
     hipLaunchKernelGGL(lts_merge_start_kernel<3>, grid, block, 0, st, a);
     for (int r = 1; r <= max_visited; r++)
